@@ -1,0 +1,416 @@
+"""Pins of the oracle's time step against what the paper and the mathematics
+fix: fixed points, closed-form recurrences, conservation budgets, analytic
+single-phase and advection-diffusion solutions, the acoustic speed implied by
+the coupled equations of state, exact lattice projections and symmetry."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import CS2, Oracle
+
+# ----------------------------------------------------------------- helpers
+
+
+def uniform_fields(shape, alpha_g, u_g, u_l, dp_k=0.0):
+    D = len(shape)
+    ug = np.empty((D,) + shape)
+    ul = np.empty((D,) + shape)
+    for c in range(D):
+        ug[c] = u_g[c]
+        ul[c] = u_l[c]
+    return dict(alpha_g=np.full(shape, alpha_g), u_g=ug, u_l=ul, dp_k=np.full(shape, dp_k))
+
+
+def cfg2(nx, ny, **kw):
+    return workloads._base("D2Q9", nx=nx, ny=ny, up_axis=1, **kw)
+
+
+# --------------------------------------------------------- fixed points (P4, P5)
+
+
+def test_uniform_rest_state_is_a_fixed_point():
+    cfg = cfg2(12, 10, rho_l=10.0, drag="cgw", kappa_I=1e-4, psi_g=0.2, psi_l=0.1)
+    o = Oracle(cfg, uniform_fields((10, 12), 0.2, (0, 0), (0, 0)))
+    f0 = {s: v.copy() for s, v in o.f.items()}
+    o.step(40)
+    for s in f0:
+        assert np.max(np.abs(o.f[s] - f0[s])) < 1e-13, s
+
+
+def test_uniform_rest_state_in_a_closed_channel_is_a_fixed_point():
+    cfg = cfg2(9, 11, rho_l=100.0, drag="cgw", kappa_I=1e-4, gamma=1.0, n_gamma=3,
+               bc={"x-": "wall", "x+": "wall", "y-": "inlet", "y+": "outlet"},
+               alpha_in_max=0.2, alpha_in_min=0.2, n_ramp=10.0)
+    o = Oracle(cfg, uniform_fields((11, 9), 0.2, (0, 0), (0, 0)))
+    f0 = {s: v.copy() for s, v in o.f.items()}
+    o.step(30)
+    for s in f0:
+        assert np.max(np.abs(o.f[s] - f0[s])) < 1e-13, s
+
+
+@pytest.mark.parametrize("drag", ["const", "cgw"])
+def test_uniform_drift_flux_state_is_a_fixed_point(drag):
+    """Eq. (124): buoyancy (R-1) g balanced by the drag at the slip
+    |u_g - u_l|^2 = alpha_g alpha_l (R-1) g / K_I, with K_I = kappa_I Lambda
+    (Eqs. (135)-(136)) for the Clift-Grace-Weber model.  In a periodic box the
+    constant kinematic-pressure gradient of Eqs. (121)-(122) is carried by the
+    mixture-mean reference density."""
+    R, g, ag = 10.0, 1e-6 / 9.0, 0.2
+    al = 1.0 - ag
+    if drag == "const":
+        K = 1e-2
+        kw = dict(drag="const", K_I=K)
+        slip = math.sqrt(ag * al * (R - 1.0) * g / K)
+    else:
+        kappa = 9.667e-5
+        kw = dict(drag="cgw", kappa_I=kappa)
+        slip = math.sqrt(ag * al * (R - 1.0) * g / (kappa * ag * al * (ag + al * R)))
+    cfg = cfg2(6, 8, rho_g=1.0, rho_l=R, g_hat=g, rho_ref="mixture_mean", **kw)
+    ul = (0.003, -0.002)
+    ug = (ul[0], ul[1] + slip)
+    o = Oracle(cfg, uniform_fields((8, 6), ag, ug, ul))
+    o.step(25)
+    r = o.read()
+    assert np.max(np.abs(r["u_g"][1] - ug[1])) < 1e-13
+    assert np.max(np.abs(r["u_l"][1] - ul[1])) < 1e-13
+    assert np.max(np.abs(r["u_g"][0] - ug[0])) < 1e-15
+    assert np.max(np.abs(r["alpha_g"] - ag)) < 1e-14
+    assert np.max(np.abs(r["dp_k"])) < 1e-15
+    # a slip 1 % off is not a fixed point: the test can fail
+    o2 = Oracle(cfg, uniform_fields((8, 6), ag, (ul[0], ul[1] + 1.01 * slip), ul))
+    o2.step(5)
+    assert np.max(np.abs(o2.read()["u_g"][1] - (ul[1] + 1.01 * slip))) > 1e-8
+
+
+# ------------------------------------------------------ slip relaxation (P6)
+
+
+def test_uniform_slip_relaxation_recurrence_and_momentum():
+    """With gravity off and a uniform state, only the drag of Eq. (6) acts:
+    u_g gains F_gl/(alpha_g rho_g), u_l gains -F_gl/(alpha_l rho_l) per step
+    (Eqs. (24), (26)), so du = u_l - u_g follows
+    du <- du - K (1/alpha_g + 1/(R alpha_l)) |du| du and the mixture
+    momentum rho_g alpha_g u_g + rho_l alpha_l u_l is constant."""
+    R, K, ag = 4.0, 0.05, 0.3
+    cfg = cfg2(4, 4, rho_g=1.0, rho_l=R, drag="const", K_I=K, sigma_grad=False)
+    ug, ul = np.array([0.01, 0.005]), np.array([-0.002, 0.001])
+    o = Oracle(cfg, uniform_fields((4, 4), ag, ug, ul))
+    du = ul - ug
+    k = K * (1.0 / ag + 1.0 / (R * (1.0 - ag)))
+    mom0 = 1.0 * ag * ug + R * (1.0 - ag) * ul
+    for _ in range(30):
+        o.step()
+        du = du - k * np.linalg.norm(du) * du
+        r = o.read()
+        du_o = r["u_l"][:, 0, 0] - r["u_g"][:, 0, 0]
+        assert np.max(np.abs(du_o - du)) < 1e-15
+        mom = ag * r["u_g"][:, 0, 0] + R * (1.0 - ag) * r["u_l"][:, 0, 0]
+        assert np.max(np.abs(mom - mom0)) < 1e-15
+    # with the sigma . grad(alpha) / alpha term on, the deviation is only
+    # second order in the velocity change per step
+    cfg["sigma_grad"] = True
+    o = Oracle(cfg, uniform_fields((4, 4), ag, ug, ul))
+    du = ul - ug
+    for _ in range(30):
+        o.step()
+        du = du - k * np.linalg.norm(du) * du
+    r = o.read()
+    assert np.max(np.abs(r["u_l"][:, 0, 0] - r["u_g"][:, 0, 0] - du)) < 1e-8
+
+
+# ------------------------------------------------- dashpot + lagged sources
+
+
+def test_dashpot_and_lag_recurrence():
+    """Uniform state, no drag, no gravity, the sigma . grad(alpha) term off:
+    each step adds S'' to eps (zeroth moment of Eq. (42)) and S'' u to u (the
+    S u term of Eqs. (24), (26)), with S'_g = -gamma |u_g|^2 (eps_g - 1)
+    (Eq. (128)), S'_l = -gamma |u_l|^2 (phi eps_l - 1) with
+    phi eps_l = 1 + (eps_g - 1)/R (Eqs. (32), (131), third strategy), both
+    refreshed only when t is a multiple of n_gamma (Eq. (133))."""
+    R, gam, ng = 2.0, 1.0, 3
+    cfg = cfg2(4, 4, rho_g=1.0, rho_l=R, gamma=gam, n_gamma=ng, sigma_grad=False)
+    ug, ul = np.array([0.02, 0.01]), np.array([0.01, -0.005])
+    dp = 1e-3
+    o = Oracle(cfg, uniform_fields((4, 4), 0.4, ug, ul, dp_k=dp))
+    eg, el = 1.0 + dp / CS2, 1.0
+    ug_, ul_ = ug.copy(), ul.copy()
+    S2g = S2l = None
+    for t in range(20):
+        if t % ng == 0:
+            S2g = -gam * ug_ @ ug_ * (eg - 1.0)
+            S2l = -gam * ul_ @ ul_ * ((1.0 + (eg - 1.0) / R) - 1.0)
+        eg, el = eg + S2g, el + S2l
+        ug_, ul_ = ug_ * (1.0 + S2g), ul_ * (1.0 + S2l)
+        o.step()
+        m = o.moments()
+        assert abs(m["eps_g"][0, 0] - eg) < 1e-14
+        assert abs(m["eps_l"][0, 0] - el) < 1e-14
+        assert np.max(np.abs(m["u_g"][:, 0, 0] - ug_)) < 1e-15
+        assert np.max(np.abs(m["u_l"][:, 0, 0] - ul_)) < 1e-15
+
+
+# --------------------------------------------------------- budgets (P7)
+
+
+@pytest.mark.parametrize("renorm", [False, True])
+def test_periodic_budgets(renorm):
+    """Periodic box, smooth random fields, gamma = 0, n_gamma = 1:
+    sum_x S_phi = 0 (streaming of the lattice kinetic scheme, Eq. (95),
+    conserves the sum of f_beta, whose equilibrium has unit zeroth moment), so
+    sum_x eps_phi is conserved; sum_x u changes by sum_x G (first moments of
+    Eqs. (36), (42)); sum_x alpha_phi changes by omega_alpha sum_x (alpha^B - a)
+    (zero without the renormalisation of Eq. (93)); the drag of Eq. (6)
+    exchanges momentum between the phases pointwise."""
+    ny = nx = 24
+    cfg = cfg2(nx, ny, rho_g=1.0, rho_l=5.0, drag="const", K_I=0.02, g_hat=2e-6,
+               rho_ref="mixture_mean", psi_g=0.1, psi_l=0.05, omega_g=0.8, omega_l=1.1,
+               omega_ag=1.3, omega_al=1.6, renormalize=renorm)
+    f = workloads.smooth_random_2d(nx, ny, seed=3, amp_u=3e-3, amp_p=1e-3, alpha0=0.4, amp_a=0.2)
+    o = Oracle(cfg, f)
+    d0 = o.diag()
+    for _ in range(15):
+        m0 = o.moments()
+        o.step()
+        L = o.last
+        m1 = o.moments()
+        assert abs(L["S_g"].sum()) < 1e-13 and abs(L["S_l"].sum()) < 1e-13
+        assert abs(m1["eps_g"].sum() - m0["eps_g"].sum()) < 1e-12
+        assert abs(m1["eps_l"].sum() - m0["eps_l"].sum()) < 1e-12
+        for ph in "gl":
+            dG = m1["u_" + ph].sum(axis=(1, 2)) - m0["u_" + ph].sum(axis=(1, 2)) - L["G_" + ph].sum(axis=(1, 2))
+            assert np.max(np.abs(dG)) < 1e-15
+            da = m1["a_" + ph].sum() - m0["a_" + ph].sum()
+            om = cfg["omega_a" + ph]
+            assert abs(da - om * (m0["alpha_" + ph] - m0["a_" + ph]).sum()) < 1e-12
+            if not renorm:
+                assert abs(da) < 1e-12
+        ex = 1.0 * m0["alpha_g"] * L["drag_g"] + 5.0 * m0["alpha_l"] * L["drag_l"]
+        assert np.max(np.abs(ex)) < 1e-20
+    d1 = o.diag()
+    assert d1["nonfinite"] == 0
+    assert abs(d1["eps_g"] - d0["eps_g"]) < 1e-11
+
+
+# ---------------------------------------------------- Taylor-Green (P8)
+
+
+def test_single_phase_limit_taylor_green_decay():
+    """R = 1, equal viscosities, identical initial f_g and f_l, uniform
+    alpha = 1/2: both momentum schemes reduce to the incompressible-equilibrium
+    BGK scheme, whose velocity recovers Eq. (67) with the viscosity of
+    Eq. (65).  The Taylor-Green vortex must then decay as exp(-2 nu k^2 t)."""
+    N, U0, omega = 48, 0.01, 1.0
+    nu = CS2 * (1.0 / omega - 0.5)
+    k = 2 * np.pi / N
+    x = np.arange(N)[None, :]
+    y = np.arange(N)[:, None]
+    ux = U0 * np.sin(k * x) * np.cos(k * y)
+    uy = -U0 * np.cos(k * x) * np.sin(k * y)
+    p = -U0 * U0 / 4.0 * (np.cos(2 * k * x) + np.cos(2 * k * y))
+    u = np.stack([ux, uy])
+    cfg = cfg2(N, N, rho_g=1.0, rho_l=1.0, omega_g=omega, omega_l=omega, drag="const", K_I=0.0)
+    o = Oracle(cfg, dict(alpha_g=np.full((N, N), 0.5), u_g=u, u_l=u.copy(), dp_k=p))
+    T = 400
+    o.step(T)
+    r = o.read()
+    amp = np.sum(r["u_g"][0] * np.sin(k * x) * np.cos(k * y)) / np.sum((np.sin(k * x) * np.cos(k * y)) ** 2)
+    rate = -math.log(amp / U0) / T
+    assert abs(rate / (2 * nu * k * k) - 1.0) < 2e-3
+    rel = np.linalg.norm(r["u_g"] - r["u_l"]) / np.linalg.norm(r["u_g"])
+    assert rel < 1e-4
+    # a wrong viscosity (nu without the -1/2) would be 50 % off: the test can fail
+    assert abs((CS2 / omega) / nu - 1.0) > 0.1
+
+
+# ---------------------------------------------------- Gaussian pulse (P9)
+
+
+def test_gaussian_volume_fraction_pulse():
+    """Eqs. (71)-(72) advect alpha with u and diffuse it with
+    chi = c_s^2 (1/omega_alpha - 1/2) (Eqs. (87)-(88)).  With R = 1 and a
+    uniform velocity in both phases, a Gaussian pulse follows the analytic
+    advection-diffusion solution."""
+    N, T, s0, A, ab = 64, 200, 6.0, 0.1, 0.3
+    U = np.array([0.01, 0.005])
+    om_a = 1.5
+    chi = CS2 * (1.0 / om_a - 0.5)
+    x = np.arange(N)[None, :].astype(float)
+    y = np.arange(N)[:, None].astype(float)
+    x0 = y0 = N / 2.0
+
+    def pulse(t):
+        s2 = s0 * s0 + 2.0 * chi * t
+        out = np.zeros((N, N))
+        for ix in (-1, 0, 1):
+            for iy in (-1, 0, 1):
+                dx = x - x0 - U[0] * t + ix * N
+                dy = y - y0 - U[1] * t + iy * N
+                out += A * (s0 * s0 / s2) * np.exp(-(dx * dx + dy * dy) / (2.0 * s2))
+        return ab + out
+
+    cfg = cfg2(N, N, rho_g=1.0, rho_l=1.0, omega_ag=om_a, omega_al=om_a, drag="const", K_I=0.0)
+    o = Oracle(cfg, uniform_fields((N, N), 0.0, U, U) | dict(alpha_g=pulse(0.0)))
+    o.step(T)
+    r = o.read()
+    ref = pulse(T)
+    err = np.linalg.norm(r["alpha_g"] - ref) / np.linalg.norm(ref - ab)
+    assert err < 5e-3, err
+    assert np.max(np.abs(r["u_g"] - U[:, None, None])) < 1e-15
+    # the same pulse with the diffusivity off by the -1/2 is far away
+    chi_wrong = CS2 / om_a
+    s2w = s0 * s0 + 2.0 * chi_wrong * T
+    assert np.linalg.norm(A * (s0 * s0 / s2w) - A * (s0 * s0 / (s0 * s0 + 2 * chi * T))) > 1e-3
+
+
+def _slab_pulse_error(N, T, s0, U, ny=4, om_a=1.5, A=0.1, ab=0.3):
+    chi = CS2 * (1.0 / om_a - 0.5)
+    x = np.arange(N)[None, :].astype(float)
+
+    def pulse(t):
+        s2 = s0 * s0 + 2.0 * chi * t
+        out = np.zeros((ny, N))
+        for ix in (-1, 0, 1):
+            dx = x - N / 2.0 - U * t + ix * N
+            out += A * np.sqrt(s0 * s0 / s2) * np.exp(-dx * dx / (2.0 * s2))
+        return ab + out
+
+    cfg = cfg2(N, ny, rho_g=1.0, rho_l=1.0, omega_ag=om_a, omega_al=om_a)
+    ug = np.zeros((2, ny, N))
+    ug[0] = U
+    o = Oracle(cfg, dict(alpha_g=pulse(0.0), u_g=ug, u_l=ug.copy()))
+    o.step(T)
+    ref = pulse(T)
+    return np.linalg.norm(o.read()["alpha_g"] - ref) / np.linalg.norm(ref - ab)
+
+
+def test_gaussian_pulse_converges_at_second_order():
+    """Under the diffusive refinement of Sec. 2.2 (x/2, t*4, u/2, fixed
+    omega_alpha so chi in lattice units is fixed) the error against the
+    analytic 1D advection-diffusion solution falls four-fold (Eq. (90))."""
+    e1 = _slab_pulse_error(64, 100, 4.0, 0.02)
+    e2 = _slab_pulse_error(128, 400, 8.0, 0.01)
+    assert e1 < 5e-3
+    assert 3.5 < e1 / e2 < 4.5, (e1, e2)
+
+
+# --------------------------------------------------- mixture sound speed
+
+
+def test_mixture_sound_speed_from_coupled_eos():
+    """Linearising Eqs. (19)-(20) with the gas equation of state (Eq. (27))
+    and the liquid one (Eq. (32), p/rho_l = c_s^2 eps_g / R) gives
+    d2 eps_g/dt2 = c_s^2 (alpha_g + alpha_l / R) d2 eps_g/dx2: a pressure wave
+    travels at c_s sqrt(alpha_g + alpha_l / R)."""
+    N, R, ag = 160, 5.0, 0.3
+    cfg = cfg2(N, 1, rho_g=1.0, rho_l=R, omega_g=1.2, omega_l=1.2, drag="const", K_I=0.0)
+    k = 2 * np.pi / N
+    x = np.arange(N)[None, :]
+    f = uniform_fields((1, N), ag, (0, 0), (0, 0))
+    f["dp_k"] = 1e-7 * np.cos(k * x)
+    o = Oracle(cfg, f)
+    amps = []
+    for _ in range(900):
+        o.step()
+        amps.append(np.sum(o.read()["dp_k"] * np.cos(k * x)))
+    amps = np.array(amps)
+    zc = [i + amps[i] / (amps[i] - amps[i + 1]) for i in range(len(amps) - 1) if amps[i] * amps[i + 1] < 0]
+    period = 2.0 * np.mean(np.diff(zc))
+    c_meas = 2 * np.pi / period / k
+    c_th = math.sqrt(CS2 * (ag + (1.0 - ag) / R))
+    assert abs(c_meas / c_th - 1.0) < 1e-2, (c_meas, c_th)
+    # the gas-only speed c_s or the liquid EOS with R instead of 1/R differ by > 50 %
+    assert abs(math.sqrt(CS2) / c_th - 1.0) > 0.5
+
+
+# ---------------------------------------------- lattice projection (P3)
+
+
+def _proj(f2, lat2, axis_c, lat1):
+    """Sum D2Q9 populations over the transverse velocity for each velocity
+    along axis_c; returns D1Q3-ordered populations."""
+    out = []
+    for q1 in range(lat1.Q):
+        sel = [q for q in range(lat2.Q) if lat2.v[q, axis_c] == lat1.v[q1, 0]]
+        out.append(sum(f2[q] for q in sel))
+    return np.stack(out)
+
+
+def test_d2q9_with_uniform_transverse_fields_projects_onto_d1q3_periodic():
+    from oracle import d1q3, d2q9
+    N = 20
+    base = dict(rho_g=1.0, rho_l=3.0, drag="cgw", kappa_I=1e-3, g_hat=5e-6, rho_ref="mixture_mean",
+                psi_g=0.1, psi_l=0.05, gamma=0.5, n_gamma=2, omega_g=0.9, omega_l=1.3,
+                omega_ag=1.2, omega_al=1.4)
+    xs = np.arange(N)
+    a = 0.3 + 0.1 * np.sin(2 * np.pi * xs / N + 0.3)
+    ug = 0.01 * np.cos(2 * np.pi * xs / N)
+    ul = 0.004 * np.sin(2 * np.pi * 2 * xs / N)
+    dp = 1e-4 * np.cos(2 * np.pi * xs / N + 1.0)
+    c1 = workloads._base("D1Q3", nx=N, up_axis=0, **base)
+    o1 = Oracle(c1, dict(alpha_g=a, u_g=ug[None], u_l=ul[None], dp_k=dp))
+    c2 = workloads._base("D2Q9", nx=N, ny=3, up_axis=0, **base)
+    z = np.zeros((3, N))
+    o2 = Oracle(c2, dict(alpha_g=np.broadcast_to(a, (3, N)), u_g=np.stack([z + ug, z]),
+                         u_l=np.stack([z + ul, z]), dp_k=np.broadcast_to(dp, (3, N))))
+    o1.step(12)
+    o2.step(12)
+    l1, l2 = d1q3(), d2q9()
+    for s in o1.f:
+        pj = _proj(o2.f[s][:, 1, :], l2, 0, l1) if False else _proj(o2.f[s][:, 1, :][:, None, :], l2, 0, l1)[:, 0, :]
+        assert np.max(np.abs(pj - o1.f[s])) < 1e-13, s
+
+
+def test_d2q9_channel_along_y_projects_onto_d1q3_tube():
+    """Inlet/outlet rules of Tables 1-2 on a D2Q9 channel along y with
+    x-uniform fields reproduce the D1Q3 tube populations summed over v_x."""
+    from oracle import d1q3, d2q9
+    N = 24
+    base = dict(rho_g=1.0, rho_l=2.0, drag="const", K_I=1e-2, K_W=1e-2, g_hat=1e-6, rho_ref="liquid",
+                omega_g=0.6, omega_l=0.6, omega_ag=1.5, omega_al=1.5, gamma=1.0, n_gamma=4,
+                alpha_in_max=0.8, alpha_in_min=0.01, ug_in_max=1e-2, ug_in_min=7e-4,
+                ul_in_max=1e-3, ul_in_min=0.0, n_ramp=40.0)
+    ys = np.arange(N)
+    a = 0.01 + 0.02 * np.exp(-((ys - 5.0) / 4.0) ** 2)
+    ug = 1e-3 * np.exp(-((ys - 8.0) / 5.0) ** 2)
+    c1 = workloads._base("D1Q3", nx=N, up_axis=0, bc={"x-": "inlet", "x+": "outlet"}, **base)
+    o1 = Oracle(c1, dict(alpha_g=a, u_g=ug[None], u_l=np.zeros((1, N)), dp_k=np.zeros(N)))
+    c2 = workloads._base("D2Q9", nx=2, ny=N, up_axis=1, bc={"y-": "inlet", "y+": "outlet"}, **base)
+    col = lambda v: np.broadcast_to(v[:, None], (N, 2)).copy()
+    o2 = Oracle(c2, dict(alpha_g=col(a), u_g=np.stack([np.zeros((N, 2)), col(ug)]),
+                         u_l=np.zeros((2, N, 2)), dp_k=np.zeros((N, 2))))
+    o1.step(60)
+    o2.step(60)
+    l1, l2 = d1q3(), d2q9()
+    for s in o1.f:
+        pj = _proj(o2.f[s][:, :, 0], l2, 1, l1)
+        assert np.max(np.abs(pj - o1.f[s])) < 1e-13, s
+
+
+# ------------------------------------------------------ mirror symmetry
+
+
+def test_mirror_symmetry_channel():
+    """x -> nx-1-x maps the channel onto itself (walls swap); a mirror-
+    symmetric initial state (u_x odd, everything else even) stays symmetric."""
+    nx, ny = 10, 14
+    cfg, f = workloads.channel_2d(nx=nx, ny=ny, alpha_in=0.1, n_ramp=20.0)
+    cfg["rho_l"] = 50.0
+    cfg["g_hat"] = 1e-6 / 49.0
+    cfg["n_gamma"] = 3
+    rnd = workloads.smooth_random_2d(nx, ny, seed=7, amp_u=2e-3, amp_p=1e-4, alpha0=0.1, amp_a=0.03)
+    sym = lambda a: 0.5 * (a + a[..., ::-1])
+    f["alpha_g"] = sym(rnd["alpha_g"])
+    f["u_g"] = np.stack([0.5 * (rnd["u_g"][0] - rnd["u_g"][0][..., ::-1]), sym(rnd["u_g"][1])])
+    f["u_l"] = np.stack([0.5 * (rnd["u_l"][0] - rnd["u_l"][0][..., ::-1]), sym(rnd["u_l"][1])])
+    f["dp_k"] = sym(rnd["dp_k"])
+    f["inlet_noise"] = sym(f["inlet_noise"])
+    o = Oracle(cfg, f)
+    o.step(25)
+    r = o.read()
+    assert np.max(np.abs(r["alpha_g"] - r["alpha_g"][:, ::-1])) < 1e-15
+    assert np.max(np.abs(r["u_g"][0] + r["u_g"][0][:, ::-1])) < 1e-15
+    assert np.max(np.abs(r["u_l"][1] - r["u_l"][1][:, ::-1])) < 1e-15
+    assert np.max(np.abs(r["dp_k"] - r["dp_k"][:, ::-1])) < 1e-15

@@ -1,0 +1,152 @@
+"""Seeded synthetic inputs shared by the oracle-side and the GPU-side tests and
+by the benchmark.
+
+This module holds none of the method's arithmetic: only parameter constants
+(lattice units), random draws from ``numpy.random.default_rng(seed)`` and
+closed-form initial fields.  Derived constants (drag factor, buoyancy, inlet
+slip velocity) are written out as numbers; the tests recompute them with the
+oracle's mapping helpers.
+
+A workload is ``(cfg, fields)``: ``cfg`` a dict of scheme parameters, ``fields``
+a dict of NumPy FP64 arrays in C order with x fastest -- scalars ``(ny, nx)`` /
+``(nz, ny, nx)``, vectors with a leading component axis ``(D, ...)`` ordered
+(x, y, z), and ``inlet_noise`` over the inlet face (the face's own grid).
+"""
+import numpy as np
+
+# Bubble-column physics shared by the channel and column workloads:
+# kappa_I = 3 C_d / (4 d) with C_d = 0.66, d = 3 mm -> 165 1/m; the TEST #4
+# invariant c tau = 5.8586e-7 m^2/s gives kappa_hat = 9.667e-5, and
+# (R - 1) g_hat = 1e-6 at R = 1000 gives g_hat = 1.001e-9.
+KAPPA_HAT_3MM = 9.667e-5
+G_HAT_R1000 = 1.001e-9
+# terminal slip at alpha_g = 0.05 with the Clift-Grace-Weber factor
+UG_IN_R1000 = 3.30e-3
+
+
+def _base(lattice, **kw):
+    cfg = dict(lattice=lattice, rho_g=1.0, rho_l=10.0, omega_g=0.25, omega_l=0.25,
+               psi_g=0.0, psi_l=0.0, omega_ag=1.5, omega_al=1.5, drag="const", K_I=0.0,
+               kappa_I=0.0, K_W=0.0, g_hat=0.0, rho_ref="liquid", gamma=0.0, n_gamma=1,
+               alpha_min=1e-6, renormalize=True, sigma_grad=True)
+    cfg.update(kw)
+    return cfg
+
+
+def periodic_box_2d(nx=64, ny=64, seed=0, R=10.0):
+    """D2Q9 periodic box, two phases at rest, gas fraction 0.1 plus four
+    seeded sinusoidal modes of total amplitude <= 0.01, gravity on."""
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(0.0, 2.0 * np.pi, 4)
+    chi = rng.uniform(0.0, 2.0 * np.pi, 4)
+    x = np.arange(nx)[None, :]
+    y = np.arange(ny)[:, None]
+    pert = np.zeros((ny, nx))
+    for m in range(1, 5):
+        pert += np.sin(2 * np.pi * m * x / nx + theta[m - 1]) * np.sin(2 * np.pi * m * y / ny + chi[m - 1])
+    alpha = 0.1 + 0.01 / 4.0 * pert
+    cfg = _base("D2Q9", nx=nx, ny=ny, rho_g=1.0, rho_l=R, drag="cgw", kappa_I=KAPPA_HAT_3MM,
+                g_hat=1e-6 / (R - 1.0), up_axis=1, rho_ref="mixture_mean")
+    fields = dict(alpha_g=alpha, u_g=np.zeros((2, ny, nx)), u_l=np.zeros((2, ny, nx)),
+                  dp_k=np.zeros((ny, nx)))
+    return cfg, fields
+
+
+def channel_2d(nx=1024, ny=1024, seed=0, alpha_in=0.05, noise=0.1, n_ramp=833.0):
+    """D2Q9 bubble-column-like channel: inlet at y = 0, outlet at y = ny - 1,
+    no-slip walls at x = 0 and x = nx - 1, R = 1000, Clift-Grace-Weber drag
+    for 3 mm bubbles, gas injected with fraction alpha_in and per-node
+    uniform noise of +-noise (relative), fixed in time."""
+    rng = np.random.default_rng(seed)
+    inlet_noise = 1.0 + noise * rng.uniform(-1.0, 1.0, nx)
+    cfg = _base("D2Q9", nx=nx, ny=ny, rho_g=1.0, rho_l=1000.0, drag="cgw",
+                kappa_I=KAPPA_HAT_3MM, g_hat=G_HAT_R1000, up_axis=1, rho_ref="liquid",
+                gamma=1.0, n_gamma=200,
+                bc={"x-": "wall", "x+": "wall", "y-": "inlet", "y+": "outlet"},
+                alpha_in_max=alpha_in, alpha_in_min=alpha_in / 10.0,
+                ug_in_max=UG_IN_R1000, ug_in_min=UG_IN_R1000 / 10.0,
+                ul_in_max=0.0, ul_in_min=0.0, n_ramp=n_ramp)
+    fields = dict(alpha_g=np.full((ny, nx), alpha_in / 10.0), u_g=np.zeros((2, ny, nx)),
+                  u_l=np.zeros((2, ny, nx)), dp_k=np.zeros((ny, nx)), inlet_noise=inlet_noise)
+    return cfg, fields
+
+
+def blob_field_3d(n, nblobs, seed=0, peak=0.3, rmin=4.0, rmax=12.0, cut=4.0):
+    """Sum of Gaussian blobs (peak 0.3, radii U[rmin, rmax]) at uniform
+    centres in a periodic n^3 box (minimum-image distances), truncated at
+    cut * r_b, clamped to [0, peak].  Returns (nz, ny, nx)."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, n, (nblobs, 3))
+    radii = rng.uniform(rmin, rmax, nblobs)
+    field = np.zeros((n, n, n))
+    for (cx, cy, cz), r in zip(centres, radii):
+        h = int(np.ceil(cut * r))
+        offs = np.arange(-h, h + 1)
+        ix = (np.floor(cx).astype(int) + offs) % n
+        iy = (np.floor(cy).astype(int) + offs) % n
+        iz = (np.floor(cz).astype(int) + offs) % n
+        dx = np.floor(cx) + offs - cx
+        dy = np.floor(cy) + offs - cy
+        dz = np.floor(cz) + offs - cz
+        r2 = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2
+        blob = np.where(r2 <= (cut * r) ** 2, peak * np.exp(-r2 / (2.0 * r * r)), 0.0)
+        field[np.ix_(iz, iy, ix)] += blob
+    return np.clip(field, 0.0, peak)
+
+
+def column_3d(n=256, nblobs=256, seed=0):
+    """D3Q19 periodic column, up = +z, R = 1000, Clift-Grace-Weber drag for
+    3 mm bubbles, seeded Gaussian gas blobs, both phases at rest."""
+    alpha = blob_field_3d(n, nblobs, seed)
+    cfg = _base("D3Q19", nx=n, ny=n, nz=n, rho_g=1.0, rho_l=1000.0, drag="cgw",
+                kappa_I=KAPPA_HAT_3MM, g_hat=G_HAT_R1000, up_axis=2, rho_ref="mixture_mean",
+                gamma=1.0, n_gamma=200)
+    fields = dict(alpha_g=alpha, u_g=np.zeros((3, n, n, n)), u_l=np.zeros((3, n, n, n)),
+                  dp_k=np.zeros((n, n, n)))
+    return cfg, fields
+
+
+def smooth_random_2d(nx, ny, seed=0, amp_u=1e-3, amp_p=1e-4, alpha0=0.3, amp_a=0.05, modes=3):
+    """Smooth periodic random fields (low Fourier modes) for parity and
+    budget tests: every field moves, nothing is at a fixed point."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(nx)[None, :] / nx
+    y = np.arange(ny)[:, None] / ny
+
+    def field(amp):
+        f = np.zeros((ny, nx))
+        for kx in range(modes + 1):
+            for ky in range(modes + 1):
+                if kx == 0 and ky == 0:
+                    continue
+                a, ph1, ph2 = rng.normal(), rng.uniform(0, 2 * np.pi), rng.uniform(0, 2 * np.pi)
+                f += a * np.sin(2 * np.pi * kx * x + ph1) * np.sin(2 * np.pi * ky * y + ph2)
+        return amp * f / max(1e-300, np.abs(f).max())
+
+    alpha = alpha0 + field(amp_a)
+    u_g = np.stack([field(amp_u), field(amp_u)])
+    u_l = np.stack([field(amp_u), field(amp_u)])
+    dp_k = field(amp_p)
+    return dict(alpha_g=alpha, u_g=u_g, u_l=u_l, dp_k=dp_k)
+
+
+def smooth_random_3d(n, seed=0, amp_u=1e-3, amp_p=1e-4, alpha0=0.3, amp_a=0.05, modes=2):
+    rng = np.random.default_rng(seed)
+    g = np.arange(n) / n
+    z, y, x = g[:, None, None], g[None, :, None], g[None, None, :]
+
+    def field(amp):
+        f = np.zeros((n, n, n))
+        for _ in range(6):
+            k = rng.integers(0, modes + 1, 3)
+            if not k.any():
+                k[0] = 1
+            ph = rng.uniform(0, 2 * np.pi, 3)
+            f += rng.normal() * (np.sin(2 * np.pi * k[0] * x + ph[0]) * np.sin(2 * np.pi * k[1] * y + ph[1])
+                                 * np.sin(2 * np.pi * k[2] * z + ph[2]))
+        return amp * f / max(1e-300, np.abs(f).max())
+
+    alpha = alpha0 + field(amp_a)
+    u_g = np.stack([field(amp_u) for _ in range(3)])
+    u_l = np.stack([field(amp_u) for _ in range(3)])
+    return dict(alpha_g=alpha, u_g=u_g, u_l=u_l, dp_k=field(amp_p))
