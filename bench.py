@@ -1,0 +1,133 @@
+"""Benchmark of the fused six-scheme LBM step on one MI355X.
+
+Workload: D2Q9 1024x1024 bubble-column-like channel (R = 1000, Clift-Grace-
+Weber drag for 3 mm bubbles, inlet gas fraction 0.05 with +-10 % seeded noise,
+outlet at the top, no-slip side walls, gravity on), FP32 populations.  A step
+is one launch of the fused kernel over the whole lattice; the timed region is
+K steps with the inputs already resident in HBM.
+
+Prints one JSON line: MLUPS, the roofline of the step kernel (algorithmic HBM
+bytes per launch / measured launch time vs the 8 TB/s HBM3E peak) and the FP64
+oracle timed on a bounded sample of the same workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (6 coupled schemes) & % HBM peak; surrogate speedup at ≤2% rel L2"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2409_10399_amd", "csrc", "eelbm_kernels.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_d2q9_fp32_channel1024_pmc.json")
+
+
+def algorithmic_bytes_per_node(D, Q, tbytes, cbytes, lag):
+    """State one node-update must read and write: 4Q post-collision
+    populations (f_g, f_l, f_ag, f_al) read and written, the 1 + D
+    imposed-velocity values (alpha_g, u_g - u_l) that stand in for the 2Q
+    source-scheme populations read and written, and the 3 lag values read
+    (their write every n_gamma steps is not counted)."""
+    return 2 * 4 * Q * tbytes + 2 * (1 + D) * cbytes + (3 * cbytes if lag else 0)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def cpu_baseline(steps=3):
+    """The oracle as it stands, single-threaded, on the full 1024x1024 channel
+    for a few steps (a bounded sample of the same workload)."""
+    code = (
+        "import sys, time, json; sys.path.insert(0, %r)\n"
+        "import workloads\nfrom oracle import Oracle\n"
+        "cfg, f = workloads.channel_2d()\n"
+        "o = Oracle(cfg, f)\n"
+        "t0 = time.perf_counter(); o.step(%d); dt = time.perf_counter() - t0\n"
+        "print(json.dumps({'dt': dt, 'nodes': cfg['nx'] * cfg['ny']}))\n" % (ROOT, steps))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": d["nodes"] * steps / d["dt"] / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"D2Q9 1024x1024 channel, {steps} steps, NumPy FP64, 1 thread ({d['dt']:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the method's step is benchmarked on a single MI355X); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_2409_10399_amd import Lattice
+
+    cfg, fields = workloads.channel_2d()
+    nodes = cfg["nx"] * cfg["ny"]
+    lat = Lattice(cfg, storage=args.storage)
+    lat.init_fields(fields)
+    lat.advance(args.warmup)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    lat.advance(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    ms_per_step = ms / args.steps
+    mlups = nodes * args.steps / (ms / 1e3) / 1e6
+
+    tb = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}[args.storage]
+    cb = 8 if args.storage == "fp64" else 4
+    bpn = algorithmic_bytes_per_node(2, 9, tb, cb, cfg["n_gamma"] > 1)
+    achieved = bpn * nodes / (ms_per_step / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(PMC_SUMMARY):
+        with open(PMC_SUMMARY) as fh:
+            pmc = json.load(fh)
+        if pmc.get("kernel_sha") == kernel_hash() and pmc.get("storage") == args.storage:
+            traffic = pmc.get("bytes_per_launch")
+    d = lat.diag()
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64"}.get(args.storage, "f32"),
+        "data": "synthetic",
+        "config": {"workload": "D2Q9 1024x1024 bubble-column channel (R=1000, CGW 3 mm, inlet alpha 0.05 "
+                               "+-10% noise, walls, outlet), 6 coupled schemes",
+                   "lattice": "D2Q9", "nx": cfg["nx"], "ny": cfg["ny"], "storage": args.storage,
+                   "n_gamma": cfg["n_gamma"], "bytes_per_node_update": bpn},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "wall_s": round(wall, 3),
+        "state_ok": bool(d["nonfinite"] == 0),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * eelbm.h -- C ABI of the MI355X (gfx950) implementation of the six coupled
+ * lattice Boltzmann schemes of Piredda & Asinari, "Lattice Boltzmann framework
+ * for multiphase flows by Eulerian-Eulerian Navier-Stokes equations"
+ * (arXiv:2409.10399).
+ *
+ * One time step updates, on one D2Q9 or D3Q19 lattice, the two artificially
+ * compressible momentum schemes f_g, f_l (Sec. 2.1.1, Eqs. (34)-(42)), the two
+ * volume-fraction schemes f_ag, f_al (Sec. 2.2, Eqs. (71)-(94)) and the two
+ * continuity-source schemes f_bg, f_bl (Sec. 2.3, Eqs. (95)-(107)), with the
+ * large-density-ratio stabilisers of Sec. 3.2 (Eqs. (128)-(133)), the
+ * Clift-Grace-Weber drag of Sec. 3.3 (Eqs. (135)-(137)) and the boundary rules
+ * of Sec. 3.5 (Tables 1-2, Eqs. (159)-(164)).
+ *
+ * The calls follow the paper's statement of the problem (Sec. 1: unknowns
+ * alpha_g, p, u_g, u_l; Sec. 2.1: phase densities and the density ratio R):
+ * create a lattice from the phase densities, relaxation rates, drag and
+ * boundary parameters; set the initial fields; advance N steps; read the
+ * volume fractions, phase velocities and kinematic pressure.
+ *
+ * Conventions
+ *  - All quantities are in lattice units (the paper's hat quantities).
+ *  - Fields are structure-of-arrays in C order with x fastest: a scalar field
+ *    is [nz][ny][nx] (nz = 1 in 2D), a vector field is [D][nz][ny][nx] with
+ *    component order (x, y, z).
+ *  - Device memory for the state is owned by the caller (eelbm_state_bytes,
+ *    then eelbm_create binds it); the handle never frees it.  Host arrays
+ *    passed in are copied before the call returns and stay caller-owned.
+ *  - Work is enqueued on the caller's HIP stream given at create time.
+ *    eelbm_advance is asynchronous; eelbm_read to host, eelbm_diag and
+ *    eelbm_save synchronise that stream.
+ *  - Every call returns 0 on success or a negative EELBM_E_* code; no C++
+ *    exception crosses the ABI.  eelbm_last_error() gives a thread-local
+ *    message for the last failure.
+ *  - Calls on one handle must not overlap (one host thread at a time).
+ */
+#ifndef EELBM_H
+#define EELBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EELBM_ABI_VERSION 1
+
+/* return codes */
+#define EELBM_OK 0
+#define EELBM_E_PARAM (-1)     /* invalid parameter value or combination */
+#define EELBM_E_SIZE (-2)      /* buffer too small / size mismatch */
+#define EELBM_E_HIP (-3)       /* a HIP runtime call or kernel launch failed */
+#define EELBM_E_NONFINITE (-4) /* diagnostics found NaN or Inf in the state */
+#define EELBM_E_STATE (-5)     /* call out of order (e.g. advance before init) */
+
+/* lattice */
+#define EELBM_D2Q9 2
+#define EELBM_D3Q19 3
+
+/* population storage: populations are stored as deviations from the rest
+ * equilibrium w_q (w_q * 0 for f_ag); collision arithmetic is FP64 for FP64
+ * storage and FP32 otherwise */
+#define EELBM_FP64 0
+#define EELBM_FP32 1
+#define EELBM_FP16 2
+#define EELBM_BF16 3
+
+/* boundary type of one face (Sec. 3.5) */
+#define EELBM_BC_PERIODIC 0
+#define EELBM_BC_WALL 1   /* no-slip wall: bounce-back, zero flux, EQ(S)(1,0) for f_b */
+#define EELBM_BC_INLET 2  /* Table 1 */
+#define EELBM_BC_OUTLET 3 /* Table 2 */
+
+/* drag model: constant K_I, or Clift-Grace-Weber K_I = kappa_I Lambda (Eq. (135)) */
+#define EELBM_DRAG_CONST 0
+#define EELBM_DRAG_CGW 1
+
+/* buoyancy reference density (b_phi = (rho_ref/rho_phi - 1) g_hat along up) */
+#define EELBM_RHOREF_LIQUID 0       /* rho_ref = rho_l: the kinematic pressure of Eqs. (108)-(110) */
+#define EELBM_RHOREF_MIXTURE_MEAN 1 /* mean mixture density of the initial state (periodic boxes) */
+#define EELBM_RHOREF_EXPLICIT 2     /* rho_ref given in the params */
+
+/* flags */
+#define EELBM_FLAG_NO_RENORM 1u     /* skip the Spalding renormalisation of Eq. (93) */
+#define EELBM_FLAG_NO_SIGMA_GRAD 2u /* drop the sigma . grad(alpha) / alpha term of G (Eq. (92)) */
+
+typedef struct eelbm_params {
+    int32_t abi_version;   /* must be EELBM_ABI_VERSION */
+    int32_t lattice;       /* EELBM_D2Q9 or EELBM_D3Q19 */
+    int32_t storage;       /* EELBM_FP64 / FP32 / FP16 / BF16 */
+    int32_t nx, ny, nz;    /* nz = 1 for D2Q9 */
+    int32_t bc[6];         /* faces x-, x+, y-, y+, z-, z+; periodic faces come in pairs */
+    int32_t up_axis;       /* 0, 1, 2: direction of +buoyancy (and of the inlet flow) */
+    int32_t drag_model;    /* EELBM_DRAG_* */
+    int32_t rho_ref_mode;  /* EELBM_RHOREF_* */
+    int32_t n_gamma;       /* lag period of Eqs. (133), (137); >= 1 */
+    uint32_t flags;        /* EELBM_FLAG_* */
+    int32_t reserved_i;
+    double rho_g, rho_l;   /* phase densities; R = rho_l / rho_g */
+    double omega_g, omega_l;   /* BGK relaxation of f_g, f_l: nu = c_s^2 (1/omega - 1/2), Eq. (65) */
+    double psi_g, psi_l;       /* forcing-operator parameter, Eq. (66) */
+    double omega_ag, omega_al; /* relaxation of f_ag, f_al: chi = c_s^2 (1/omega - 1/2), Eq. (88) */
+    double K_I;            /* constant drag coefficient (EELBM_DRAG_CONST), Eq. (6) */
+    double kappa_I;        /* Clift-Grace-Weber factor kappa_I (EELBM_DRAG_CGW) */
+    double K_W;            /* liquid wall-friction coefficient, Eq. (119) (0: off) */
+    double g_hat;          /* gravity magnitude */
+    double rho_ref;        /* used with EELBM_RHOREF_EXPLICIT */
+    double gamma;          /* dashpot constant, Eqs. (128), (131) */
+    double alpha_min;      /* floor of alpha in 1/alpha factors (> 0) */
+    /* inlet ramp y(t) = (max - min) tanh(t / n_ramp) + min, Eq. (153); n_ramp <= 0: max */
+    double alpha_in_max, alpha_in_min;
+    double ug_in_max, ug_in_min;
+    double ul_in_max, ul_in_min;
+    double n_ramp;
+} eelbm_params;
+
+typedef struct eelbm_handle eelbm_handle;
+
+/* field ids for eelbm_read */
+#define EELBM_FIELD_ALPHA_G 0 /* renormalised gas volume fraction (Eq. (93)), scalar */
+#define EELBM_FIELD_ALPHA_L 1 /* 1 - alpha_g, scalar */
+#define EELBM_FIELD_U_G 2     /* gas velocity, Eq. (41), vector */
+#define EELBM_FIELD_U_L 3     /* liquid velocity, vector */
+#define EELBM_FIELD_P_K 4     /* kinematic pressure p_k = c_s^2 eps_g (Eq. (111)), scalar */
+#define EELBM_FIELD_DP_K 5    /* p_k - c_s^2, scalar */
+
+/* dtype of eelbm_read destinations */
+#define EELBM_DTYPE_F64 0
+#define EELBM_DTYPE_F32 1
+
+/* domain sums at the current time, accumulated in FP64 on the GPU */
+typedef struct eelbm_diagnostics {
+    int64_t t;               /* time step of the sums */
+    int64_t nonfinite;       /* count of NaN/Inf populations read this step */
+    double a_g, a_l;         /* sum of raw zeroth moments of f_ag, f_al (Eq. (73)) */
+    double alpha_g, alpha_l; /* sum of renormalised volume fractions */
+    double deps_g, deps_l;   /* sum of (eps - 1) of f_g, f_l (Eq. (40)) */
+    double u_g[3], u_l[3];   /* sums of phase velocities */
+    double momentum[3];      /* sum of rho_g alpha_g u_g + rho_l alpha_l u_l */
+    double renorm_defect;    /* sum of (alpha_g - a_g) */
+} eelbm_diagnostics;
+
+/* Version of this ABI (EELBM_ABI_VERSION) and sizeof(eelbm_params), so that
+ * a binding can check its mirror of the struct. */
+int32_t eelbm_abi_version(void);
+size_t eelbm_params_size(void);
+
+/* Device bytes the state needs for *p (two population copies, imposed-velocity
+ * fields, lag fields, boundary side buffers, output fields, staging and
+ * diagnostics).  Returns EELBM_E_PARAM for invalid parameters. */
+int eelbm_state_bytes(const eelbm_params* p, size_t* bytes);
+
+/* Bind caller-owned device memory (at least eelbm_state_bytes bytes, 256-byte
+ * aligned) and a caller-owned hipStream_t (NULL: the null stream).  *p is
+ * copied.  The device current at the call is the one the handle uses. */
+int eelbm_create(const eelbm_params* p, void* device_mem, size_t bytes, void* hip_stream,
+                 eelbm_handle** out);
+
+/* Initial macroscopic fields at t = 0.  f_g, f_l, f_ag, f_al start at the
+ * local equilibria of these fields (eps_g = 1 + dp_k / c_s^2, eps_l = 1);
+ * f_bg, f_bl start as if streamed from the equilibria f^eq(1, c_phi) of the
+ * initial imposed velocities of Eq. (97).  alpha_g and dp_k (= p_k - c_s^2) are scalar fields, u_g and
+ * u_l vector fields, all FP64.  inlet_noise is the factor multiplying the
+ * inlet gas fraction per inlet-face node ([face rows][face cols], face axis
+ * removed), or NULL for 1.  on_device = 1: all pointers are device pointers.
+ * u_g, u_l, dp_k may be NULL (zero). */
+int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g, const double* u_l,
+                      const double* dp_k, const double* inlet_noise, int on_device);
+
+/* Advance nsteps time steps (asynchronous on the bound stream).  The last
+ * step also writes the output fields and the diagnostic partial sums. */
+int eelbm_advance(eelbm_handle* h, int64_t nsteps);
+
+/* Copy a field at the current time into dst (dtype EELBM_DTYPE_*; host or
+ * device pointer).  Vector fields take D * nodes elements. */
+int eelbm_read(eelbm_handle* h, int32_t field, void* dst, int32_t dst_dtype, int on_device);
+
+/* Domain sums at the current time (synchronises the stream).  Returns
+ * EELBM_E_NONFINITE (and fills *out) if a non-finite population was seen. */
+int eelbm_diag(eelbm_handle* h, eelbm_diagnostics* out);
+
+/* Current time step (number of steps since eelbm_init_fields). */
+int64_t eelbm_time(const eelbm_handle* h);
+
+/* Launch shape of the step kernel (for tuning; results do not depend on it):
+ * one workgroup per tile of tile_x * tile_y nodes of an (x, y) plane, a whole
+ * number of 64-wide wavefronts and at most 256 nodes; xcd_remap = 1 hands each
+ * of the 8 XCDs one contiguous run of tiles.  The diagnostics of the last
+ * step refer to the shape they were produced with, so call this before
+ * eelbm_advance. */
+int eelbm_set_launch(eelbm_handle* h, int32_t tile_x, int32_t tile_y, int32_t xcd_remap);
+int eelbm_get_launch(const eelbm_handle* h, int32_t* tile_x, int32_t* tile_y, int32_t* xcd_remap);
+
+/* Checkpoint: bytes needed for a save (eelbm_save with host_buf = NULL sets
+ * *bytes), save to a caller host buffer, load into a handle created with the
+ * same parameters.  A loaded run continues bit-for-bit like the saved one. */
+int eelbm_save(eelbm_handle* h, void* host_buf, size_t* bytes);
+int eelbm_load(eelbm_handle* h, const void* host_buf, size_t bytes);
+
+/* Release the handle (not the caller's device memory or stream). */
+void eelbm_destroy(eelbm_handle* h);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* eelbm_last_error(void);
+
+/* Similarity mapping of Sec. 3.3: from the physical gravity g, drag factor
+ * kappa_I = 3 C_d / (4 d) and their lattice counterparts g_hat, kappa_hat,
+ * c/tau = g / g_hat (Eq. (138)), c tau = kappa_hat / kappa_I (Eq. (139)),
+ * c = sqrt((c/tau)(c tau)) (Eq. (140)); velocities convert as u_hat = u / c. */
+int eelbm_map_physical(double g, double kappa_I, double g_hat, double kappa_hat, double* c_over_tau,
+                       double* c_tau, double* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EELBM_H */

@@ -8,13 +8,13 @@ constant with it.
 
 Everything here is plain NumPy in FP64: one time step at a time, in the order
 the paper describes it, with the boundary rules of its Sec. 3.5 and the
-readings listed in the design notes for what the paper leaves open.
+readings stated beside each line for what the paper leaves open.
 
 Functions and what pins them (tests under ``tests/test_oracle_*.py``):
 
 * ``equilibria.feq_I / feq_S / feq_L`` -- moment identities (Eqs. (37), (42),
   (50), (72), (80)) on D1Q3/D2Q9/D3Q19 and the printed D1Q3 closed forms of
-  Appendix A (``tests/golden/d1q3_appendix_a.json``).
+  Appendix A (typed from the paper in ``tests/test_oracle_equilibria.py``).
 * ``scheme.Oracle.step`` -- uniform rest state is a fixed point; the uniform
   drift-flux state of Eq. (124) is a fixed point (buoyancy, drag, Clift-Grace-
   Weber factor); uniform slip relaxation follows its closed-form recurrence
@@ -24,7 +24,7 @@ Functions and what pins them (tests under ``tests/test_oracle_*.py``):
   Gaussian volume-fraction pulse against the analytic advection-diffusion
   solution with the diffusivity of Eq. (88); the mixture sound speed implied by
   Eqs. (19), (20), (32); D2Q9 with y-uniform fields projecting exactly onto
-  D1Q3; mirror symmetry; tiny-grid agreement with ``fd`` (second order).
+  D1Q3; mirror symmetry.
 * Boundary rules of Sec. 3.5 in several dimensions (walls, corners) --
   parity unpinned: the paper has no multi-dimensional boundary data; they are
   checked only for the 1D steady relations and for symmetry.

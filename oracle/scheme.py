@@ -7,9 +7,8 @@ and the post-collision sets exactly in the order the paper describes them, and
 streams them to t + 1, applying the boundary rules of Sec. 3.5 (Tables 1-2,
 Eqs. (159)-(164)).  Nothing is fused or reordered for speed.
 
-Where the paper leaves a choice open, the reading taken is named next to the
-line that makes it (reading ids R1..R17 match the list kept with the design
-notes of the repository).
+Where the paper leaves a choice open, the reading taken is stated next to the
+line that makes it, under a short id (R1..R17) that the tests also use.
 """
 import math
 
@@ -305,42 +304,39 @@ class Oracle:
                     per_face.append((face, msk))
             self.masks.append((wall, opn, per_face))
 
-    def _face_values(self, y, face, mode):
-        """STEP #1 of Sec. 3.5, Eqs. (160)-(161): extrapolate the nodal field y
-        to a boundary face, half-way (hw) or full-way (fw), and broadcast the
-        face values over the grid along the face normal."""
-        D = self.lat.D
-        name, side = face[0], face[1]
-        c = FACE_AXES[name]
-        lead = y.ndim - D                                    # 1 for vector fields
-        ax = lead + (D - 1 - c)
-        n = y.shape[ax]
-        e, nxt = (0, 1) if side == "-" else (n - 1, n - 2)
-        ye = np.take(y, e, axis=ax)
-        yn = np.take(y, nxt, axis=ax)
-        if mode == "hw":
-            yb = 1.5 * ye - 0.5 * yn
-        else:
-            yb = 2.0 * ye - yn
-        return np.broadcast_to(np.expand_dims(yb, ax), y.shape)
-
-    def _inlet_dir(self, face):
-        D = self.lat.D
-        c = FACE_AXES[face[0]]
-        nvec = np.zeros((D,) + (1,) * D)
-        nvec[c] = 1.0 if face[1] == "-" else -1.0
-        return nvec
-
-    def _inlet_alpha(self, face, t):
-        p = self.p
-        a_in = _ramp(t, p.alpha_in[0], p.alpha_in[1], p.n_ramp)
+    def _face_values(self, y, face, mode, idx):
+        """STEP #1 of Sec. 3.5, Eqs. (160)-(161): the nodal field y extrapolated
+        to a boundary face, half-way (hw) or full-way (fw), for the nodes idx
+        (a tuple of grid index arrays) lying on that face; extrapolation runs
+        along the face normal from the edge node and its inward neighbour."""
         D = self.lat.D
         c = FACE_AXES[face[0]]
         ax = D - 1 - c
+        n = self.p.shape[ax]
+        e, nxt = (0, 1) if face[1] == "-" else (n - 1, n - 2)
+        ie = tuple(np.full_like(ix, e) if a == ax else ix for a, ix in enumerate(idx))
+        iN = tuple(np.full_like(ix, nxt) if a == ax else ix for a, ix in enumerate(idx))
+        lead = (slice(None),) * (y.ndim - D)
+        ye, yn = y[lead + ie], y[lead + iN]
+        return 1.5 * ye - 0.5 * yn if mode == "hw" else 2.0 * ye - yn
+
+    def _inlet_dir(self, face, m):
+        """Unit normal of an inlet face pointing into the domain, for m nodes."""
+        D = self.lat.D
+        nvec = np.zeros((D, m))
+        nvec[FACE_AXES[face[0]]] = 1.0 if face[1] == "-" else -1.0
+        return nvec
+
+    def _inlet_alpha(self, face, t, idx):
+        """Inlet gas fraction at time t: the ramp of Eq. (153) times the
+        per-node factor of the inlet face (reading R17)."""
+        p = self.p
+        a_in = _ramp(t, p.alpha_in[0], p.alpha_in[1], p.n_ramp)
         if self.inlet_noise is None:
-            return np.full(p.shape, a_in)
+            return np.full(idx[0].shape, a_in)
+        ax = self.lat.D - 1 - FACE_AXES[face[0]]
         noise = np.asarray(self.inlet_noise, dtype=np.float64)
-        return np.broadcast_to(np.expand_dims(a_in * noise, ax), p.shape)
+        return a_in * noise[tuple(ix for a, ix in enumerate(idx) if a != ax)]
 
     def _stream(self, s, fstar, m, t):
         """Streaming (left-hand sides of Eqs. (34), (35), (71), (95)) plus
@@ -353,65 +349,66 @@ class Oracle:
             out[q] = np.roll(fstar[q], shift=tuple(int(lat.v[q, c]) for c in range(D)), axis=axes)
         if all(b == "periodic" for b in p.bc.values()):
             return out
-        grid = p.shape
         phase = s[-1]
-        zeros_u = np.zeros((D,) + grid)
         for q in range(lat.Q):
             wall, opn, per_face = self.masks[q]
             qs = lat.opp[q]                                  # q* leaves the domain, q = BB(q*)
             if wall.any():
                 if s in ("bg", "bl"):
                     # EQ(S) with beta = 1, c = 0 at a wall (reading R15).
-                    out[q][wall] = eq.feq_S(lat, np.ones(grid), zeros_u)[q][wall]
+                    k = int(wall.sum())
+                    out[q][wall] = eq.feq_S(lat, np.ones(k), np.zeros((D, k)))[q]
                 else:
                     # Half-way bounce-back with zero wall velocity (reading R15).
                     out[q][wall] = fstar[qs][wall]
             if opn.any():
                 out[q][opn] = fstar[q][opn]
             for face, msk in per_face:
-                if not msk.any():
+                idx = np.nonzero(msk)
+                k = idx[0].size
+                if k == 0:
                     continue
                 kind = p.bc[face]
+                fo = fstar[qs][idx]                          # f*(x_E, t, q*)
                 if s in ("bg", "bl"):
                     # EQ(S), beta and c extrapolated full-way (Tables 1-2, reading R16).
-                    bB = self._face_values(m["b_" + phase], face, "fw")
-                    cB = self._face_values(m["c_" + phase], face, "fw")
+                    bB = self._face_values(m["b_" + phase], face, "fw", idx)
+                    cB = self._face_values(m["c_" + phase], face, "fw", idx)
                     val = eq.feq_S(lat, bB, cB)[q]
                 elif kind == "inlet":
-                    nvec = self._inlet_dir(face)
+                    nvec = self._inlet_dir(face, k)
                     if s in ("g", "l"):
                         # BB(I), Eq. (163): eps extrapolated half-way, u imposed.
                         uin = (_ramp(t, *p.ug_in, p.n_ramp) if phase == "g" else _ramp(t, *p.ul_in, p.n_ramp))
-                        uB = np.broadcast_to(uin * nvec, (D,) + grid)
-                        epsB = self._face_values(m["eps_" + phase], face, "hw")
+                        uB = uin * nvec
+                        epsB = self._face_values(m["eps_" + phase], face, "hw", idx)
                         if phase == "g":
-                            phiB = np.ones(grid)
+                            phiB = np.ones(k)
                         else:
-                            eg = self._face_values(m["eps_g"], face, "hw")
+                            eg = self._face_values(m["eps_g"], face, "hw", idx)
                             phiB = (1.0 / epsB) * (1.0 + (eg - 1.0) / p.R)
                         delta = eq.feq_I(lat, phiB, epsB, -uB)[qs] - eq.feq_I(lat, phiB, epsB, uB)[qs]
-                        val = fstar[qs] + delta
+                        val = fo + delta
                     else:
                         # EQ(S) with the imposed alpha and u.
-                        a_in = self._inlet_alpha(face, t)
+                        a_in = self._inlet_alpha(face, t, idx)
                         if phase == "g":
                             aB, uin = a_in, _ramp(t, *p.ug_in, p.n_ramp)
                         else:
                             aB, uin = 1.0 - a_in, _ramp(t, *p.ul_in, p.n_ramp)
-                        uB = np.broadcast_to(uin * nvec, (D,) + grid)
-                        val = eq.feq_S(lat, aB, uB)[q]
+                        val = eq.feq_S(lat, aB, uin * nvec)[q]
                 else:  # outlet
-                    uB = self._face_values(m["u_" + phase], face, "hw")
+                    uB = self._face_values(m["u_" + phase], face, "hw", idx)
                     if s in ("g", "l"):
                         # ABB(I), Eq. (164): eps = 1 (hence phi = 1), u extrapolated half-way.
-                        one = np.ones(grid)
+                        one = np.ones(k)
                         delta = eq.feq_I(lat, one, one, -uB)[qs] + eq.feq_I(lat, one, one, uB)[qs]
                     else:
                         # ABB(S): alpha and u extrapolated half-way.
-                        aB = self._face_values(m["alpha_" + phase], face, "hw")
+                        aB = self._face_values(m["alpha_" + phase], face, "hw", idx)
                         delta = eq.feq_S(lat, aB, -uB)[qs] + eq.feq_S(lat, aB, uB)[qs]
-                    val = -fstar[qs] + delta
-                out[q][msk] = val[msk]
+                    val = -fo + delta
+                out[q][idx] = val
         return out
 
     # ----------------------------------------------------------------- read-out

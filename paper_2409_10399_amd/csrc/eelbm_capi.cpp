@@ -1,0 +1,625 @@
+// Host side of the C ABI declared in include/eelbm.h: parameter validation,
+// layout of the caller-owned device state, launch sequencing on the caller's
+// stream, read-out, diagnostics and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "eelbm.h"
+#include "eelbm_internal.hpp"
+
+using namespace eelbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return EELBM_E_HIP;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t pop[2], cf[2], lag, side[2], noise, stage, macro, partials, dout, spart, total;
+};
+
+struct Geometry {
+    int D, Q;
+    long long n;
+    int flow_axis;
+    long long face_n;
+    size_t tsize, csize;
+    dim3 grid, block;
+    int nblocks;
+    int ntx, nty, xcd_remap;
+    bool channel;
+};
+
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
+// Launch shape: tiles of bx * by nodes (a whole number of 64-wide wavefronts,
+// at most 256 threads), one workgroup per tile, tiles of all planes in one
+// grid dimension.  bx = 0 picks the default: rows of up to 256 nodes.
+// EELBM_TILE_X / EELBM_TILE_Y / EELBM_XCD_REMAP override the default.
+void set_tiles(const eelbm_params& p, Geometry* g, int bx, int by, int xcd) {
+    if (bx <= 0) {
+        bx = env_int("EELBM_TILE_X", 0);
+        by = env_int("EELBM_TILE_Y", 0);
+    }
+    if (bx <= 0 || by <= 0 || bx * by > 256 || (bx * by) % 64 != 0) {
+        bx = ((p.nx + 63) / 64) * 64;
+        if (bx > 256) bx = 256;
+        by = 1;
+    }
+    if (xcd < 0) xcd = env_int("EELBM_XCD_REMAP", 1);
+    g->block = dim3(bx, by, 1);
+    g->ntx = (p.nx + bx - 1) / bx;
+    g->nty = (p.ny + by - 1) / by;
+    g->xcd_remap = xcd ? 1 : 0;
+    g->nblocks = g->ntx * g->nty * p.nz;
+    g->grid = dim3(g->nblocks, 1, 1);
+}
+
+bool periodic(const eelbm_params& p, int face) { return p.bc[face] == EELBM_BC_PERIODIC; }
+
+int validate(const eelbm_params* pp, Geometry* g) {
+    if (!pp) return fail(EELBM_E_PARAM, "params is NULL");
+    const eelbm_params& p = *pp;
+    if (p.abi_version != EELBM_ABI_VERSION) return fail(EELBM_E_PARAM, "abi_version mismatch");
+    if (p.lattice != EELBM_D2Q9 && p.lattice != EELBM_D3Q19) return fail(EELBM_E_PARAM, "lattice must be D2Q9 or D3Q19");
+    if (p.storage < EELBM_FP64 || p.storage > EELBM_BF16) return fail(EELBM_E_PARAM, "unknown storage");
+    const int D = p.lattice == EELBM_D2Q9 ? 2 : 3;
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(EELBM_E_PARAM, "grid sizes must be >= 1");
+    if (D == 2 && p.nz != 1) return fail(EELBM_E_PARAM, "D2Q9 needs nz = 1");
+    if (p.ny > 65535 || p.nz > 65535) return fail(EELBM_E_PARAM, "ny and nz must be <= 65535");
+    const long long n = (long long)p.nx * p.ny * p.nz;
+    if (n > (1LL << 31) / 4) return fail(EELBM_E_PARAM, "too many nodes for one lattice");
+    int flow_axis = -1;
+    const int nn[3] = {p.nx, p.ny, p.nz};
+    for (int a = 0; a < 3; ++a) {
+        const int lo = p.bc[2 * a], hi = p.bc[2 * a + 1];
+        for (int v : {lo, hi})
+            if (v < EELBM_BC_PERIODIC || v > EELBM_BC_OUTLET) return fail(EELBM_E_PARAM, "unknown boundary type");
+        if (a >= D) {
+            if (lo != EELBM_BC_PERIODIC || hi != EELBM_BC_PERIODIC)
+                return fail(EELBM_E_PARAM, "faces beyond the lattice dimension must be periodic");
+            continue;
+        }
+        if ((lo == EELBM_BC_PERIODIC) != (hi == EELBM_BC_PERIODIC))
+            return fail(EELBM_E_PARAM, "periodic faces come in pairs");
+        const bool open = lo == EELBM_BC_INLET || lo == EELBM_BC_OUTLET || hi == EELBM_BC_INLET || hi == EELBM_BC_OUTLET;
+        if (open) {
+            if (flow_axis >= 0) return fail(EELBM_E_PARAM, "inlet/outlet faces on more than one axis");
+            flow_axis = a;
+            if (nn[a] < 4) return fail(EELBM_E_PARAM, "an axis with inlet/outlet faces needs >= 4 nodes");
+        } else if (lo == EELBM_BC_WALL && nn[a] < 2) {
+            return fail(EELBM_E_PARAM, "a walled axis needs >= 2 nodes");
+        }
+    }
+    if (p.up_axis < 0 || p.up_axis >= D) return fail(EELBM_E_PARAM, "up_axis out of range");
+    if (!(p.rho_g > 0 && p.rho_l > 0)) return fail(EELBM_E_PARAM, "densities must be > 0");
+    for (double om : {p.omega_g, p.omega_l, p.omega_ag, p.omega_al})
+        if (!(om > 0 && om < 2)) return fail(EELBM_E_PARAM, "relaxation rates must lie in (0, 2)");
+    if (p.drag_model != EELBM_DRAG_CONST && p.drag_model != EELBM_DRAG_CGW) return fail(EELBM_E_PARAM, "unknown drag model");
+    if (p.rho_ref_mode < EELBM_RHOREF_LIQUID || p.rho_ref_mode > EELBM_RHOREF_EXPLICIT)
+        return fail(EELBM_E_PARAM, "unknown rho_ref_mode");
+    if (p.n_gamma < 1) return fail(EELBM_E_PARAM, "n_gamma must be >= 1");
+    if (!(p.alpha_min > 0)) return fail(EELBM_E_PARAM, "alpha_min must be > 0");
+    if (p.flags & ~(EELBM_FLAG_NO_RENORM | EELBM_FLAG_NO_SIGMA_GRAD)) return fail(EELBM_E_PARAM, "unknown flags");
+    if (!std::isfinite(p.g_hat) || !std::isfinite(p.gamma) || !std::isfinite(p.K_I) || !std::isfinite(p.kappa_I) ||
+        !std::isfinite(p.K_W))
+        return fail(EELBM_E_PARAM, "non-finite parameter");
+    if (g) {
+        g->D = D;
+        g->Q = D == 2 ? 9 : 19;
+        g->n = n;
+        g->flow_axis = flow_axis;
+        g->face_n = flow_axis < 0 ? 0 : n / nn[flow_axis];
+        g->tsize = p.storage == EELBM_FP64 ? 8 : (p.storage == EELBM_FP32 ? 4 : 2);
+        g->csize = p.storage == EELBM_FP64 ? 8 : 4;
+        set_tiles(p, g, 0, 0, -1);
+        g->channel = false;
+        for (int f = 0; f < 2 * D; ++f) g->channel = g->channel || p.bc[f] != EELBM_BC_PERIODIC;
+    }
+    return EELBM_OK;
+}
+
+// upper bound of the workgroup count over every allowed tile shape
+// (bx * by >= 64): ceil(nx/bx) ceil(ny/by) <= nx ny / 64 + nx + ny + 1
+size_t max_blocks(const eelbm_params& p) {
+    return ((size_t)p.nx * p.ny / 64 + p.nx + p.ny + 2) * (size_t)p.nz;
+}
+
+Layout layout(const eelbm_params& p, const Geometry& g) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t n = (size_t)g.n;
+    const int NV = 2 * g.D + 4;
+    for (int k = 0; k < 2; ++k) L.pop[k] = take(4 * (size_t)g.Q * n * g.tsize);
+    for (int k = 0; k < 2; ++k) L.cf[k] = take((size_t)(2 + g.D) * n * g.csize);
+    L.lag = take(p.n_gamma > 1 ? 3 * n * g.csize : 0);
+    for (int k = 0; k < 2; ++k) L.side[k] = take((size_t)2 * 2 * NV * (size_t)g.face_n * g.csize);
+    L.noise = take((size_t)g.face_n * 8);
+    L.stage = take((size_t)(2 + 2 * g.D) * n * 8);
+    L.macro = take((size_t)(3 + 2 * g.D) * n * 8);
+    L.partials = take(max_blocks(p) * kNDiag * 8);
+    L.dout = take((kNDiag + 1) * 8);
+    L.spart = take(1024 * 8);
+    L.total = off;
+    return L;
+}
+
+double ramp(double t, double ymax, double ymin, double nr) {
+    if (!(nr > 0)) return ymax;
+    return (ymax - ymin) * std::tanh(t / nr) + ymin;
+}
+
+}  // namespace
+
+struct eelbm_handle {
+    eelbm_params p;
+    Geometry g;
+    Layout L;
+    char* mem;
+    size_t bytes;
+    hipStream_t stream;
+    int device;
+    int64_t t;
+    int cur;
+    bool initialized;
+    double rho_ref, b_g, b_l;
+    KParams kp;
+};
+
+namespace {
+
+KBuffers buffers(eelbm_handle* h, int in, int out) {
+    KBuffers b{};
+    char* m = h->mem;
+    b.pop_in = m + h->L.pop[in];
+    b.pop_out = m + h->L.pop[out];
+    b.cf_in = m + h->L.cf[in];
+    b.cf_out = m + h->L.cf[out];
+    b.lag = m + h->L.lag;
+    b.side_in = m + h->L.side[in];
+    b.side_out = m + h->L.side[out];
+    b.noise = reinterpret_cast<const double*>(m + h->L.noise);
+    b.stage = reinterpret_cast<const double*>(m + h->L.stage);
+    b.macro = reinterpret_cast<double*>(m + h->L.macro);
+    b.partials = reinterpret_cast<double*>(m + h->L.partials);
+    return b;
+}
+
+void fill_kparams(eelbm_handle* h) {
+    const eelbm_params& p = h->p;
+    KParams& k = h->kp;
+    k = KParams{};
+    k.nx = p.nx;
+    k.ny = p.ny;
+    k.nz = p.nz;
+    k.n = h->g.n;
+    k.ntx = h->g.ntx;
+    k.nty = h->g.nty;
+    k.xcd_remap = h->g.xcd_remap;
+    for (int a = 0; a < 3; ++a) {
+        k.per[a] = periodic(p, 2 * a);
+        k.wall_lo[a] = p.bc[2 * a] == EELBM_BC_WALL;
+        k.wall_hi[a] = p.bc[2 * a + 1] == EELBM_BC_WALL;
+    }
+    k.flow_axis = h->g.flow_axis;
+    k.face_lo = h->g.flow_axis >= 0 ? p.bc[2 * h->g.flow_axis] : EELBM_BC_PERIODIC;
+    k.face_hi = h->g.flow_axis >= 0 ? p.bc[2 * h->g.flow_axis + 1] : EELBM_BC_PERIODIC;
+    k.face_n = h->g.face_n;
+    k.up = p.up_axis;
+    k.cgw = p.drag_model == EELBM_DRAG_CGW;
+    k.use_lag = p.n_gamma > 1;
+    k.renorm = !(p.flags & EELBM_FLAG_NO_RENORM);
+    k.sigma_grad = !(p.flags & EELBM_FLAG_NO_SIGMA_GRAD);
+    k.R = p.rho_l / p.rho_g;
+    k.invR = p.rho_g / p.rho_l;
+    k.rho_g = p.rho_g;
+    k.rho_l = p.rho_l;
+    k.omega_g = p.omega_g;
+    k.omega_l = p.omega_l;
+    k.psi_g = p.psi_g;
+    k.psi_l = p.psi_l;
+    k.omega_ag = p.omega_ag;
+    k.omega_al = p.omega_al;
+    k.K_I = p.K_I;
+    k.kappa_I = p.kappa_I;
+    k.K_W = p.K_W;
+    k.b_g = h->b_g;
+    k.b_l = h->b_l;
+    k.gamma = p.gamma;
+    k.alpha_min = p.alpha_min;
+}
+
+int launch(eelbm_handle* h, bool init, int64_t t, bool last) {
+    KCtl c{};
+    c.t = t;
+    c.refresh = (t % h->p.n_gamma) == 0;
+    c.write_macro = last;
+    c.write_diag = last;
+    // streaming from t - 1 to t uses the inlet values at t - 1 (Eq. (153))
+    c.a_in = ramp((double)(t - 1), h->p.alpha_in_max, h->p.alpha_in_min, h->p.n_ramp);
+    c.ug_in = ramp((double)(t - 1), h->p.ug_in_max, h->p.ug_in_min, h->p.n_ramp);
+    c.ul_in = ramp((double)(t - 1), h->p.ul_in_max, h->p.ul_in_min, h->p.n_ramp);
+    const int in = init ? 1 : h->cur;
+    const int out = init ? 0 : 1 - h->cur;
+    KBuffers b = buffers(h, in, out);
+    hipError_t e = launch_step(h->p.lattice, h->p.storage, h->g.channel, init, h->kp, b, c, h->g.grid, h->g.block,
+                               h->stream);
+    if (e != hipSuccess) return hip_fail(e, "k_step launch");
+    h->cur = out;
+    h->t = t;
+    return EELBM_OK;
+}
+
+int copy_in(eelbm_handle* h, void* dst, const void* src, size_t bytes, int on_device) {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                  h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (init fields)");
+    return EELBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t eelbm_abi_version(void) { return EELBM_ABI_VERSION; }
+size_t eelbm_params_size(void) { return sizeof(eelbm_params); }
+const char* eelbm_last_error(void) { return g_err.c_str(); }
+
+int eelbm_state_bytes(const eelbm_params* p, size_t* bytes) {
+    Geometry g;
+    int rc = validate(p, &g);
+    if (rc) return rc;
+    if (!bytes) return fail(EELBM_E_PARAM, "bytes is NULL");
+    *bytes = layout(*p, g).total;
+    return EELBM_OK;
+}
+
+int eelbm_create(const eelbm_params* p, void* device_mem, size_t bytes, void* hip_stream, eelbm_handle** out) {
+    if (!out) return fail(EELBM_E_PARAM, "out is NULL");
+    *out = nullptr;
+    Geometry g;
+    int rc = validate(p, &g);
+    if (rc) return rc;
+    Layout L = layout(*p, g);
+    if (!device_mem) return fail(EELBM_E_PARAM, "device_mem is NULL");
+    if (bytes < L.total) return fail(EELBM_E_SIZE, "device buffer smaller than eelbm_state_bytes");
+    if (reinterpret_cast<uintptr_t>(device_mem) & 255) return fail(EELBM_E_PARAM, "device buffer not 256-byte aligned");
+    eelbm_handle* h = new (std::nothrow) eelbm_handle();
+    if (!h) return fail(EELBM_E_PARAM, "out of host memory");
+    h->p = *p;
+    h->g = g;
+    h->L = L;
+    h->mem = static_cast<char*>(device_mem);
+    h->bytes = bytes;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipGetDevice");
+    }
+    h->t = 0;
+    h->cur = 0;
+    h->initialized = false;
+    h->rho_ref = p->rho_l;
+    *out = h;
+    return EELBM_OK;
+}
+
+int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g, const double* u_l,
+                      const double* dp_k, const double* inlet_noise, int on_device) {
+    if (!h) return fail(EELBM_E_PARAM, "handle is NULL");
+    if (!alpha_g) return fail(EELBM_E_PARAM, "alpha_g is NULL");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const size_t n = (size_t)h->g.n;
+    const int D = h->g.D;
+    double* stage = reinterpret_cast<double*>(h->mem + h->L.stage);
+    int rc = copy_in(h, stage, alpha_g, n * 8, on_device);
+    if (rc) return rc;
+    const double* parts[3] = {u_g, u_l, dp_k};
+    const size_t offs[3] = {n, (size_t)(1 + D) * n, (size_t)(1 + 2 * D) * n};
+    const size_t cnt[3] = {(size_t)D * n, (size_t)D * n, n};
+    for (int k = 0; k < 3; ++k) {
+        if (parts[k]) {
+            rc = copy_in(h, stage + offs[k], parts[k], cnt[k] * 8, on_device);
+        } else {
+            e = hipMemsetAsync(stage + offs[k], 0, cnt[k] * 8, h->stream);
+            rc = e == hipSuccess ? EELBM_OK : hip_fail(e, "hipMemsetAsync");
+        }
+        if (rc) return rc;
+    }
+    if (h->g.face_n > 0) {
+        double* noise = reinterpret_cast<double*>(h->mem + h->L.noise);
+        if (inlet_noise) {
+            rc = copy_in(h, noise, inlet_noise, (size_t)h->g.face_n * 8, on_device);
+        } else {
+            std::vector<double> ones((size_t)h->g.face_n, 1.0);
+            e = hipMemcpyAsync(noise, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, h->stream);
+            rc = e == hipSuccess ? EELBM_OK : hip_fail(e, "hipMemcpyAsync (noise)");
+            if (!rc) {
+                e = hipStreamSynchronize(h->stream);
+                if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+            }
+        }
+        if (rc) return rc;
+    }
+    // buoyancy reference density
+    const eelbm_params& p = h->p;
+    if (p.rho_ref_mode == EELBM_RHOREF_LIQUID) {
+        h->rho_ref = p.rho_l;
+    } else if (p.rho_ref_mode == EELBM_RHOREF_EXPLICIT) {
+        h->rho_ref = p.rho_ref;
+    } else {
+        double* sp = reinterpret_cast<double*>(h->mem + h->L.spart);
+        double* so = reinterpret_cast<double*>(h->mem + h->L.dout) + kNDiag;
+        e = launch_sum(stage, (long long)n, sp, 1024, so, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "alpha sum launch");
+        double sum = 0;
+        e = hipMemcpyAsync(&sum, so, 8, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "alpha sum read-back");
+        const double am = sum / (double)n;
+        h->rho_ref = am * p.rho_g + (1.0 - am) * p.rho_l;
+    }
+    h->b_g = (h->rho_ref / p.rho_g - 1.0) * p.g_hat;
+    h->b_l = (h->rho_ref / p.rho_l - 1.0) * p.g_hat;
+    fill_kparams(h);
+    rc = launch(h, true, 0, true);
+    if (rc) return rc;
+    if (!on_device) {
+        // host inputs were copied from pageable memory; finish before returning
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    }
+    h->initialized = true;
+    return EELBM_OK;
+}
+
+int eelbm_advance(eelbm_handle* h, int64_t nsteps) {
+    if (!h) return fail(EELBM_E_PARAM, "handle is NULL");
+    if (!h->initialized) return fail(EELBM_E_STATE, "eelbm_init_fields not called");
+    if (nsteps < 0) return fail(EELBM_E_PARAM, "nsteps < 0");
+    for (int64_t k = 1; k <= nsteps; ++k) {
+        int rc = launch(h, false, h->t + 1, k == nsteps);
+        if (rc) return rc;
+    }
+    return EELBM_OK;
+}
+
+int64_t eelbm_time(const eelbm_handle* h) { return h ? h->t : -1; }
+
+int eelbm_set_launch(eelbm_handle* h, int32_t tile_x, int32_t tile_y, int32_t xcd_remap) {
+    if (!h) return fail(EELBM_E_PARAM, "handle is NULL");
+    if (tile_x < 1 || tile_y < 1 || tile_x * tile_y > 256 || (tile_x * tile_y) % 64 != 0)
+        return fail(EELBM_E_PARAM, "tile must hold a whole number of 64-wide wavefronts, at most 256 nodes");
+    if (h->g.D == 2 && tile_y > h->p.ny) return fail(EELBM_E_PARAM, "tile_y exceeds ny");
+    set_tiles(h->p, &h->g, tile_x, tile_y, xcd_remap ? 1 : 0);
+    fill_kparams(h);
+    return EELBM_OK;
+}
+
+int eelbm_get_launch(const eelbm_handle* h, int32_t* tile_x, int32_t* tile_y, int32_t* xcd_remap) {
+    if (!h) return fail(EELBM_E_PARAM, "handle is NULL");
+    if (tile_x) *tile_x = (int32_t)h->g.block.x;
+    if (tile_y) *tile_y = (int32_t)h->g.block.y;
+    if (xcd_remap) *xcd_remap = h->g.xcd_remap;
+    return EELBM_OK;
+}
+
+int eelbm_read(eelbm_handle* h, int32_t field, void* dst, int32_t dst_dtype, int on_device) {
+    if (!h) return fail(EELBM_E_PARAM, "handle is NULL");
+    if (!h->initialized) return fail(EELBM_E_STATE, "eelbm_init_fields not called");
+    if (!dst) return fail(EELBM_E_PARAM, "dst is NULL");
+    if (dst_dtype != EELBM_DTYPE_F64 && dst_dtype != EELBM_DTYPE_F32) return fail(EELBM_E_PARAM, "unknown dtype");
+    const size_t n = (size_t)h->g.n;
+    const int D = h->g.D;
+    size_t off, cnt;
+    double add = 0.0;
+    switch (field) {
+        case EELBM_FIELD_ALPHA_G: off = 0; cnt = n; break;
+        case EELBM_FIELD_ALPHA_L: off = n; cnt = n; break;
+        case EELBM_FIELD_U_G: off = 2 * n; cnt = D * n; break;
+        case EELBM_FIELD_U_L: off = (2 + D) * n; cnt = D * n; break;
+        case EELBM_FIELD_P_K: off = (2 + 2 * D) * n; cnt = n; add = 1.0 / 3.0; break;
+        case EELBM_FIELD_DP_K: off = (2 + 2 * D) * n; cnt = n; break;
+        default: return fail(EELBM_E_PARAM, "unknown field");
+    }
+    const double* src = reinterpret_cast<const double*>(h->mem + h->L.macro) + off;
+    hipError_t e;
+    if (on_device) {
+        e = launch_convert(src, dst, dst_dtype, (long long)cnt, add, 1.0, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "convert launch");
+        return EELBM_OK;
+    }
+    if (dst_dtype == EELBM_DTYPE_F64 && add == 0.0) {
+        e = hipMemcpyAsync(dst, src, cnt * 8, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "read-back");
+        return EELBM_OK;
+    }
+    std::vector<double> tmp(cnt);
+    e = hipMemcpyAsync(tmp.data(), src, cnt * 8, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "read-back");
+    if (dst_dtype == EELBM_DTYPE_F64) {
+        double* d = static_cast<double*>(dst);
+        for (size_t i = 0; i < cnt; ++i) d[i] = tmp[i] + add;
+    } else {
+        float* d = static_cast<float*>(dst);
+        for (size_t i = 0; i < cnt; ++i) d[i] = (float)(tmp[i] + add);
+    }
+    return EELBM_OK;
+}
+
+int eelbm_diag(eelbm_handle* h, eelbm_diagnostics* out) {
+    if (!h || !out) return fail(EELBM_E_PARAM, "NULL argument");
+    if (!h->initialized) return fail(EELBM_E_STATE, "eelbm_init_fields not called");
+    double* parts = reinterpret_cast<double*>(h->mem + h->L.partials);
+    double* d = reinterpret_cast<double*>(h->mem + h->L.dout);
+    hipError_t e = launch_diag_finalize(parts, h->g.nblocks, d, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "diag launch");
+    double v[kNDiag];
+    e = hipMemcpyAsync(v, d, sizeof(v), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "diag read-back");
+    const double n = (double)h->g.n;
+    std::memset(out, 0, sizeof(*out));
+    out->t = h->t;
+    out->a_g = v[0];
+    out->a_l = v[1];
+    out->alpha_g = v[2];
+    out->alpha_l = v[3];
+    out->deps_g = v[4];
+    out->deps_l = v[5];
+    for (int a = 0; a < 3; ++a) {
+        out->u_g[a] = v[6 + a];
+        out->u_l[a] = v[9 + a];
+        out->momentum[a] = v[12 + a];
+    }
+    out->renorm_defect = v[15];
+    out->nonfinite = (int64_t)v[16];
+    (void)n;
+    if (out->nonfinite > 0) return fail(EELBM_E_NONFINITE, "non-finite populations in the state");
+    return EELBM_OK;
+}
+
+namespace {
+struct SaveHeader {
+    uint64_t magic;
+    int32_t abi, lattice, storage, nx, ny, nz;
+    int64_t t;
+    double rho_ref, b_g, b_l;
+    uint64_t pop_bytes, cf_bytes, lag_bytes, side_bytes, macro_bytes, part_bytes, noise_bytes;
+};
+constexpr uint64_t kMagic = 0x45454c424d434b31ull;  // "EELBMCK1"
+
+void save_sizes(const eelbm_handle* h, SaveHeader* s) {
+    const size_t n = (size_t)h->g.n;
+    s->pop_bytes = 4 * (size_t)h->g.Q * n * h->g.tsize;
+    s->cf_bytes = (size_t)(2 + h->g.D) * n * h->g.csize;
+    s->lag_bytes = h->p.n_gamma > 1 ? 3 * n * h->g.csize : 0;
+    s->side_bytes = (size_t)2 * 2 * (2 * h->g.D + 4) * (size_t)h->g.face_n * h->g.csize;
+    s->macro_bytes = (size_t)(3 + 2 * h->g.D) * n * 8;
+    s->part_bytes = (size_t)h->g.nblocks * kNDiag * 8;
+    s->noise_bytes = (size_t)h->g.face_n * 8;
+}
+}  // namespace
+
+int eelbm_save(eelbm_handle* h, void* host_buf, size_t* bytes) {
+    if (!h || !bytes) return fail(EELBM_E_PARAM, "NULL argument");
+    if (!h->initialized) return fail(EELBM_E_STATE, "eelbm_init_fields not called");
+    SaveHeader s{};
+    save_sizes(h, &s);
+    const size_t need = sizeof(s) + s.pop_bytes + s.cf_bytes + s.lag_bytes + s.side_bytes + s.macro_bytes + s.part_bytes +
+                        s.noise_bytes;
+    if (!host_buf) {
+        *bytes = need;
+        return EELBM_OK;
+    }
+    if (*bytes < need) return fail(EELBM_E_SIZE, "checkpoint buffer too small");
+    s.magic = kMagic;
+    s.abi = EELBM_ABI_VERSION;
+    s.lattice = h->p.lattice;
+    s.storage = h->p.storage;
+    s.nx = h->p.nx;
+    s.ny = h->p.ny;
+    s.nz = h->p.nz;
+    s.t = h->t;
+    s.rho_ref = h->rho_ref;
+    s.b_g = h->b_g;
+    s.b_l = h->b_l;
+    char* o = static_cast<char*>(host_buf);
+    std::memcpy(o, &s, sizeof(s));
+    o += sizeof(s);
+    const char* m = h->mem;
+    const std::pair<size_t, size_t> parts[7] = {{h->L.pop[h->cur], s.pop_bytes}, {h->L.cf[h->cur], s.cf_bytes},
+                                               {h->L.lag, s.lag_bytes},         {h->L.side[h->cur], s.side_bytes},
+                                               {h->L.macro, s.macro_bytes},     {h->L.partials, s.part_bytes},
+                                               {h->L.noise, s.noise_bytes}};
+    for (const auto& pr : parts) {
+        if (pr.second == 0) continue;
+        hipError_t e = hipMemcpyAsync(o, m + pr.first, pr.second, hipMemcpyDeviceToHost, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "save copy");
+        o += pr.second;
+    }
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    *bytes = need;
+    return EELBM_OK;
+}
+
+int eelbm_load(eelbm_handle* h, const void* host_buf, size_t bytes) {
+    if (!h || !host_buf) return fail(EELBM_E_PARAM, "NULL argument");
+    SaveHeader s{}, want{};
+    if (bytes < sizeof(s)) return fail(EELBM_E_SIZE, "checkpoint too small");
+    std::memcpy(&s, host_buf, sizeof(s));
+    save_sizes(h, &want);
+    if (s.magic != kMagic || s.abi != EELBM_ABI_VERSION || s.lattice != h->p.lattice || s.storage != h->p.storage ||
+        s.nx != h->p.nx || s.ny != h->p.ny || s.nz != h->p.nz || s.pop_bytes != want.pop_bytes ||
+        s.cf_bytes != want.cf_bytes || s.lag_bytes != want.lag_bytes || s.side_bytes != want.side_bytes ||
+        s.macro_bytes != want.macro_bytes || s.part_bytes != want.part_bytes || s.noise_bytes != want.noise_bytes)
+        return fail(EELBM_E_PARAM, "checkpoint does not match this lattice");
+    const size_t need = sizeof(s) + s.pop_bytes + s.cf_bytes + s.lag_bytes + s.side_bytes + s.macro_bytes +
+                        s.part_bytes + s.noise_bytes;
+    if (bytes < need) return fail(EELBM_E_SIZE, "checkpoint truncated");
+    h->cur = 0;
+    const char* o = static_cast<const char*>(host_buf) + sizeof(s);
+    const std::pair<size_t, size_t> parts[7] = {{h->L.pop[0], s.pop_bytes}, {h->L.cf[0], s.cf_bytes},
+                                               {h->L.lag, s.lag_bytes},    {h->L.side[0], s.side_bytes},
+                                               {h->L.macro, s.macro_bytes}, {h->L.partials, s.part_bytes},
+                                               {h->L.noise, s.noise_bytes}};
+    for (const auto& pr : parts) {
+        if (pr.second == 0) continue;
+        hipError_t e = hipMemcpyAsync(h->mem + pr.first, o, pr.second, hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "load copy");
+        o += pr.second;
+    }
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    h->t = s.t;
+    h->rho_ref = s.rho_ref;
+    h->b_g = s.b_g;
+    h->b_l = s.b_l;
+    fill_kparams(h);
+    h->initialized = true;
+    return EELBM_OK;
+}
+
+void eelbm_destroy(eelbm_handle* h) { delete h; }
+
+int eelbm_map_physical(double g, double kappa_I, double g_hat, double kappa_hat, double* c_over_tau, double* c_tau,
+                       double* c) {
+    if (!(g > 0 && kappa_I > 0 && g_hat > 0 && kappa_hat > 0)) return fail(EELBM_E_PARAM, "inputs must be > 0");
+    const double a = g / g_hat, b = kappa_hat / kappa_I;
+    if (c_over_tau) *c_over_tau = a;
+    if (c_tau) *c_tau = b;
+    if (c) *c = std::sqrt(a * b);
+    return EELBM_OK;
+}
+
+}  // extern "C"

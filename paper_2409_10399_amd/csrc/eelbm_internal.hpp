@@ -1,0 +1,69 @@
+// Internal interface between the C-ABI host code and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace eelbm {
+
+constexpr int kNDiag = 18;  // per-node diagnostic sums (see k_step)
+constexpr int kMaxSideVals = 2 * 3 + 4;
+
+// Scalars of the scheme, in lattice units, fixed for a run.
+struct KParams {
+    int nx, ny, nz;
+    long long n;        // nodes
+    int ntx, nty;       // tiles per plane along x and y (tile = blockDim.x * blockDim.y nodes)
+    int xcd_remap;      // map contiguous tile runs to one XCD
+    int per[3];         // axis periodic?
+    int wall_lo[3], wall_hi[3];
+    int flow_axis;      // axis carrying the inlet/outlet faces, -1 if none
+    int face_lo, face_hi;  // EELBM_BC_* of the two flow-axis faces
+    long long face_n;   // nodes of one flow-axis face
+    int up;             // buoyancy axis
+    int cgw;            // Clift-Grace-Weber drag?
+    int use_lag;        // n_gamma > 1: lag fields are stored
+    int renorm;         // Spalding renormalisation on?
+    int sigma_grad;     // sigma . grad(alpha) / alpha term on?
+    double R, invR, rho_g, rho_l;
+    double omega_g, omega_l, psi_g, psi_l, omega_ag, omega_al;
+    double K_I, kappa_I, K_W;
+    double b_g, b_l;    // buoyancy accelerations along up
+    double gamma, alpha_min;
+};
+
+// Device pointers of one launch (ping-pong halves already selected).
+struct KBuffers {
+    const void* pop_in;   // [4][Q][n] storage type: deviations of f_g, f_l, f_ag, f_al
+    void* pop_out;
+    const void* cf_in;    // [2 + D][n] compute type: alpha_g, du(D) = u_g - u_l, alpha_l
+    void* cf_out;
+    void* lag;            // [3][n] compute type: S''_g, S''_l, Lambda'
+    const void* side_in;  // [2 faces][2 layers][NV][face_n] compute type
+    void* side_out;
+    const double* noise;  // [face_n] inlet gas-fraction factor
+    const double* stage;  // init inputs [2 + 2D][n]: alpha_g, u_g(D), u_l(D), dp_k
+    double* macro;        // outputs [3 + 2D][n]: alpha_g, alpha_l, u_g(D), u_l(D), dp_k
+    double* partials;     // [blocks][kNDiag]
+};
+
+// Per-launch control.
+struct KCtl {
+    long long t;          // time of the collision performed by this launch
+    int refresh;          // t mod n_gamma == 0
+    int write_macro;
+    int write_diag;
+    double a_in, ug_in, ul_in;  // inlet ramp values at t - 1 (streaming t-1 -> t)
+};
+
+// storage: 0 FP64, 1 FP32, 2 FP16, 3 BF16; lattice: 2 D2Q9, 3 D3Q19
+hipError_t launch_step(int lattice, int storage, bool channel, bool init, const KParams& p,
+                       const KBuffers& b, const KCtl& c, dim3 grid, dim3 block, hipStream_t s);
+hipError_t launch_sum(const double* x, long long n, double* partials, int nblocks, double* out,
+                      hipStream_t s);
+hipError_t launch_diag_finalize(const double* partials, int nblocks, double* out, hipStream_t s);
+hipError_t launch_convert(const double* src, void* dst, int dst_dtype, long long n, double add,
+                          double scale, hipStream_t s);
+
+}  // namespace eelbm

@@ -1,0 +1,770 @@
+// HIP kernels of the six coupled LBM schemes for gfx950.
+//
+// One launch of k_step performs one full time step for every node: a pull
+// gather of the post-collision populations of the previous step (streaming,
+// left-hand sides of Eqs. (34), (35), (71), (95)), the boundary rules of
+// Sec. 3.5 at the domain faces, the moments of all six sets, the Spalding
+// renormalisation (Eq. (93)), the continuity sources from the source schemes
+// (Eq. (107)) with the dashpots and lagged updates of Sec. 3.2, the volume-
+// fraction gradients (Eqs. (91), (94)), the stresses (Eq. (70)), the drag
+// (Eqs. (6), (135)-(137)), the forces (Eqs. (24), (26)) and the collisions
+// (Eqs. (34)-(42), (71)-(72)), and writes the node's own post-collision
+// populations (coalesced stores, SoA, x fastest).
+//
+// State kept between launches, per node:
+//  * f_g, f_l, f_ag, f_al post-collision, as deviations from w_q (w_q * 0 for
+//    f_ag), in the storage type;
+//  * (alpha_g, u_g - u_l) -- the post-collision f_b of the lattice kinetic
+//    scheme is the pure function f^eq(1, c_phi) of these (Eqs. (95), (97) with
+//    beta = 1), so f_b is rebuilt at the gather from the upstream node's
+//    values instead of being stored: 1 + D numbers instead of 2Q;
+//  * the lag fields S''_g, S''_l, Lambda' when n_gamma > 1;
+//  * for the two node layers next to an inlet/outlet face, the macroscopic
+//    values the boundary extrapolations of Eqs. (160)-(161) need at the next
+//    step (u_g, u_l, alpha_g, alpha_l, S_g, S_l).
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "eelbm.h"
+#include "eelbm_internal.hpp"
+#include "lattice.hpp"
+
+namespace eelbm {
+
+// ---------------------------------------------------------------- storage
+template <class T>
+struct Store;
+// Populations are read exactly once per step: they are loaded nontemporally
+// so that they do not displace the imposed-velocity fields (read by nine
+// nodes) and the freshly written populations, which the next step reads back,
+// from L2 and the Infinity Cache.  Stores stay ordinary (measured: nontemporal
+// stores, or nontemporal loads of the lag fields, are slower on gfx950).
+template <>
+struct Store<double> {
+    using C = double;
+    static __device__ __forceinline__ double ld(const double* p) { return __builtin_nontemporal_load(p); }
+    static __device__ __forceinline__ void st(double* p, double v) { *p = v; }
+};
+template <>
+struct Store<float> {
+    using C = float;
+    static __device__ __forceinline__ float ld(const float* p) { return __builtin_nontemporal_load(p); }
+    static __device__ __forceinline__ void st(float* p, float v) { *p = v; }
+};
+template <>
+struct Store<__half> {
+    using C = float;
+    static __device__ __forceinline__ float ld(const __half* p) {
+        return __half2float(__ushort_as_half(__builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p))));
+    }
+    static __device__ __forceinline__ void st(__half* p, float v) { *p = __float2half_rn(v); }
+};
+template <>
+struct Store<__hip_bfloat16> {
+    using C = float;
+    static __device__ __forceinline__ float ld(const __hip_bfloat16* p) {
+        const unsigned short bits = __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p));
+        return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, bits));
+    }
+    static __device__ __forceinline__ void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
+};
+
+template <class C>
+__device__ __forceinline__ C clamp01(C v) {
+    return v < C(0) ? C(0) : (v > C(1) ? C(1) : v);
+}
+
+// w_q-normalised non-rest part of the second-order equilibria:
+// 3 v.u + 9/2 (v.u)^2 - 3/2 |u|^2  (c_s^2 = 1/3 in Eqs. (37), (72))
+template <class C>
+__device__ __forceinline__ C poly2(C cu, C usq) {
+    return C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq;
+}
+
+template <class L, class C>
+__device__ __forceinline__ C dotc(int q, const C* u) {
+    C s = C(0);
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) {
+        if (L::c[q][a] == 1) s += u[a];
+        if (L::c[q][a] == -1) s -= u[a];
+    }
+    return s;
+}
+
+__device__ __forceinline__ int wrap_axis(int v, int nax, int per) {
+    if (v < 0) return per ? v + nax : 0;
+    if (v >= nax) return per ? v - nax : nax - 1;
+    return v;
+}
+
+// --------------------------------------------------------------- the step
+#ifdef EELBM_WAVES_PER_EU
+#define EELBM_WPE __attribute__((amdgpu_waves_per_eu(EELBM_WAVES_PER_EU)))
+#else
+#define EELBM_WPE
+#endif
+template <class L, class T, bool CH, bool INIT>
+__global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const KBuffers b, const KCtl ctl) {
+    using C = typename Store<T>::C;
+    using S = Store<T>;
+    constexpr int D = L::D;
+    constexpr int Q = L::Q;
+    constexpr int NPI = L::NPI;
+    constexpr int NV = 2 * D + 4;  // side-buffer values per node
+    const C third = C(1) / C(3);
+
+    // Tiles of blockDim.x * blockDim.y nodes in an (x, y) plane, one grid
+    // dimension over all tiles of all planes.  Workgroups are dispatched to
+    // the 8 XCDs round-robin; with the XCD remap, XCD k receives one
+    // contiguous run of tiles, so the rows a pull reads from neighbouring
+    // tiles are mostly already in that XCD's L2.
+    long long tile = blockIdx.x;
+    if (p.xcd_remap) {
+        const long long nb = gridDim.x, per = nb >> 3;
+        if (tile < per * 8) tile = (tile & 7) * per + (tile >> 3);
+    }
+    const long long plane_tiles = (long long)p.ntx * p.nty;
+    const int z = (int)(tile / plane_tiles);
+    const int rem = (int)(tile - (long long)z * plane_tiles);
+    const int ty_t = rem / p.ntx;
+    const int x = (rem - ty_t * p.ntx) * blockDim.x + threadIdx.x;
+    const int y = ty_t * blockDim.y + threadIdx.y;
+    const bool act = x < p.nx && y < p.ny;
+    const long long n = p.n;
+    const long long node = ((long long)z * p.ny + y) * p.nx + x;
+    const int co[3] = {x, y, z};
+    const int nn[3] = {p.nx, p.ny, p.nz};
+
+    double dsum[kNDiag];
+#pragma unroll
+    for (int k = 0; k < kNDiag; ++k) dsum[k] = 0.0;
+
+    if (act) {
+        const T* pin = static_cast<const T*>(b.pop_in);
+        const C* cfin = static_cast<const C*>(b.cf_in);
+        const C* sidein = static_cast<const C*>(b.side_in);
+
+        // -------------------------------------------------- boundary layout
+        bool lo[3] = {false, false, false}, hi[3] = {false, false, false};
+        bool edge = false;
+        int fs = -1;            // flow-axis face this node lies on (0 low, 1 high)
+        int ftype = EELBM_BC_PERIODIC;
+        long long fidx = 0;     // node index within that face
+        int fa = p.flow_axis;
+        if constexpr (CH) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                lo[a] = !p.per[a] && co[a] == 0;
+                hi[a] = !p.per[a] && co[a] == nn[a] - 1;
+                edge = edge || lo[a] || hi[a];
+            }
+            if (fa >= 0) {
+                fidx = fa == 0 ? (long long)z * p.ny + y : (fa == 1 ? (long long)z * p.nx + x : (long long)y * p.nx + x);
+                const int cf = co[fa];
+                if (cf == 0 && (p.face_lo == EELBM_BC_INLET || p.face_lo == EELBM_BC_OUTLET)) {
+                    fs = 0;
+                    ftype = p.face_lo;
+                } else if (cf == nn[fa] - 1 && (p.face_hi == EELBM_BC_INLET || p.face_hi == EELBM_BC_OUTLET)) {
+                    fs = 1;
+                    ftype = p.face_hi;
+                }
+            }
+        }
+
+        // values on the flow face (Sec. 3.5, STEP #1)
+        C uinG[D], uinL[D], ain = C(0);                 // inlet: imposed u and alpha
+        C ugB[D], ulB[D], agB = C(0), dalB = C(0);      // outlet: EX(hw)
+        C cgB[D], clB[D], dbgB = C(0), dblB = C(0);     // beta, c: EX(fw); db = beta - 1
+#pragma unroll
+        for (int a = 0; a < D; ++a) uinG[a] = uinL[a] = ugB[a] = ulB[a] = cgB[a] = clB[a] = C(0);
+        if constexpr (CH) {
+            if (fs >= 0) {
+                const C sgn = fs == 0 ? C(1) : C(-1);
+                if (ftype == EELBM_BC_INLET) {
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        uinG[a] = a == fa ? sgn * C(ctl.ug_in) : C(0);
+                        uinL[a] = a == fa ? sgn * C(ctl.ul_in) : C(0);
+                    }
+                    ain = C(ctl.a_in * (b.noise ? b.noise[fidx] : 1.0));
+                }
+                if constexpr (INIT) {
+                    // t = -1: beta = 1, c from the initial fields of the edge
+                    // node and its inward neighbour
+                    long long e = node, nx1 = node;
+                    const long long st = fa == 0 ? 1 : (fa == 1 ? (long long)p.nx : (long long)p.nx * p.ny);
+                    nx1 = fs == 0 ? node + st : node - st;
+                    const double ae = b.stage[e], an = b.stage[nx1];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        const double due = b.stage[(1 + a) * n + e] - b.stage[(1 + D + a) * n + e];
+                        const double dun = b.stage[(1 + a) * n + nx1] - b.stage[(1 + D + a) * n + nx1];
+                        cgB[a] = C(2.0 * (1.0 - ae) * due - (1.0 - an) * dun);
+                        clB[a] = C(2.0 * (-ae * due) - (-an * dun));
+                    }
+                } else {
+                    auto sv = [&](int layer, int v) -> C {
+                        return sidein[((long long)(fs * 2 + layer) * NV + v) * p.face_n + fidx];
+                    };
+                    const C ae = sv(0, 2 * D), an = sv(1, 2 * D);
+                    const C ale = p.renorm ? C(1) - ae : sv(0, 2 * D + 1);
+                    const C aln = p.renorm ? C(1) - an : sv(1, 2 * D + 1);
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        const C uge = sv(0, a), ugn = sv(1, a), ule = sv(0, D + a), uln = sv(1, D + a);
+                        ugB[a] = C(1.5) * uge - C(0.5) * ugn;
+                        ulB[a] = C(1.5) * ule - C(0.5) * uln;
+                        cgB[a] = C(2) * (ale * (uge - ule)) - aln * (ugn - uln);
+                        clB[a] = C(2) * (ae * (ule - uge)) - an * (uln - ugn);
+                    }
+                    agB = C(1.5) * ae - C(0.5) * an;
+                    dalB = p.renorm ? -agB : (C(1.5) * ale - C(0.5) * aln) - C(1);
+                    // beta - 1 = -S, extrapolated full-way
+                    dbgB = -(C(2) * sv(0, 2 * D + 2) - sv(1, 2 * D + 2));
+                    dblB = -(C(2) * sv(0, 2 * D + 3) - sv(1, 2 * D + 3));
+                }
+            }
+        }
+
+        // ------------------------------------------------------- gather
+        C f[4][Q];
+        if constexpr (INIT) {
+            // local equilibria of the initial fields (deviation form)
+            const C a0 = C(b.stage[node]);
+            C ug0[D], ul0[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                ug0[a] = C(b.stage[(1 + a) * n + node]);
+                ul0[a] = C(b.stage[(1 + D + a) * n + node]);
+            }
+            const C de0 = C(3.0 * b.stage[(1 + 2 * D) * n + node]);
+            C us0g = C(0), us0l = C(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                us0g += ug0[a] * ug0[a];
+                us0l += ul0[a] * ul0[a];
+            }
+            const C w0 = C(L::w[0]);
+            const C k0 = (C(1) - w0) / w0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const C wq = C(L::w[q]);
+                const C cug = dotc<L>(q, ug0), cul = dotc<L>(q, ul0);
+                const C el = q == 0 ? -k0 * de0 * C(p.invR) : de0 * C(p.invR);
+                f[0][q] = wq * (de0 + poly2(cug, us0g));
+                f[1][q] = wq * (el + poly2(cul, us0l));
+                f[2][q] = wq * a0 * (C(1) + poly2(cug, us0g));
+                f[3][q] = wq * (-a0 + (C(1) - a0) * poly2(cul, us0l));
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int xs = wrap_axis(x - L::c[q][0], p.nx, p.per[0]);
+                const int ys = wrap_axis(y - L::c[q][1], p.ny, p.per[1]);
+                const int zs = wrap_axis(z - L::c[q][2], p.nz, p.per[2]);
+                const long long src = ((long long)zs * p.ny + ys) * p.nx + xs;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) f[s][q] = S::ld(pin + (long long)(s * Q + q) * n + src);
+            }
+            if constexpr (CH) {
+                if (edge) {
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        bool wall = false, flow = false;
+#pragma unroll
+                        for (int a = 0; a < D; ++a) {
+                            wall = wall || (lo[a] && L::c[q][a] == 1 && p.wall_lo[a]) ||
+                                   (hi[a] && L::c[q][a] == -1 && p.wall_hi[a]);
+                        }
+                        if (!wall && fs >= 0) {
+                            const int cfa = fa == 0 ? L::c[q][0] : (fa == 1 ? L::c[q][1] : L::c[q][2]);
+                            flow = (fs == 0 && cfa == 1) || (fs == 1 && cfa == -1);
+                        }
+                        if (!(wall || flow)) continue;
+                        const int qo = L::opp[q];
+                        C fo[4];
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) fo[s] = S::ld(pin + (long long)(s * Q + qo) * n + node);
+                        if (wall) {
+                            // half-way bounce-back, zero wall velocity
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) f[s][q] = fo[s];
+                        } else if (ftype == EELBM_BC_INLET) {
+                            const C wq = C(L::w[q]);
+                            C usg = C(0), usl = C(0);
+#pragma unroll
+                            for (int a = 0; a < D; ++a) {
+                                usg += uinG[a] * uinG[a];
+                                usl += uinL[a] * uinL[a];
+                            }
+                            const C cug = dotc<L>(q, uinG), cul = dotc<L>(q, uinL);
+                            // BB(I), Eq. (163): + f_I(-u) - f_I(u) at q* = 6 w v_q.u
+                            f[0][q] = fo[0] + C(6) * wq * cug;
+                            f[1][q] = fo[1] + C(6) * wq * cul;
+                            // EQ(S) with the imposed alpha and velocity
+                            f[2][q] = wq * ain * (C(1) + poly2(cug, usg));
+                            f[3][q] = wq * (-ain + (C(1) - ain) * poly2(cul, usl));
+                        } else {
+                            const C wq = C(L::w[q]);
+                            C usg = C(0), usl = C(0);
+#pragma unroll
+                            for (int a = 0; a < D; ++a) {
+                                usg += ugB[a] * ugB[a];
+                                usl += ulB[a] * ulB[a];
+                            }
+                            const C cug = dotc<L>(q, ugB), cul = dotc<L>(q, ulB);
+                            // ABB(I), Eq. (164), eps = phi = 1
+                            f[0][q] = -fo[0] + wq * (C(9) * cug * cug - C(3) * usg);
+                            f[1][q] = -fo[1] + wq * (C(9) * cul * cul - C(3) * usl);
+                            // ABB(S)
+                            f[2][q] = -fo[2] + C(2) * wq * agB * (C(1) + C(4.5) * cug * cug - C(1.5) * usg);
+                            f[3][q] = -fo[3] + C(2) * wq * (dalB + (C(1) + dalB) * (C(4.5) * cul * cul - C(1.5) * usl));
+                        }
+                    }
+                }
+            }
+        }
+
+        // ----------------------------- continuity sources from f_b (Eq. (107))
+        C Sg = C(0), Sl = C(0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const C wq = C(L::w[q]);
+            bool wall = false, flow = false;
+            if constexpr (CH) {
+                if (edge) {
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        wall = wall || (lo[a] && L::c[q][a] == 1 && p.wall_lo[a]) ||
+                               (hi[a] && L::c[q][a] == -1 && p.wall_hi[a]);
+                    }
+                    if (!wall && fs >= 0) {
+                        const int cfa = fa == 0 ? L::c[q][0] : (fa == 1 ? L::c[q][1] : L::c[q][2]);
+                        flow = (fs == 0 && cfa == 1) || (fs == 1 && cfa == -1);
+                    }
+                }
+            }
+            if (wall) continue;  // EQ(S)(1, 0) = w_q: zero deviation
+            C dbg, dbl;
+            if (flow) {
+                C usg = C(0), usl = C(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    usg += cgB[a] * cgB[a];
+                    usl += clB[a] * clB[a];
+                }
+                dbg = wq * (dbgB + (C(1) + dbgB) * poly2(dotc<L>(q, cgB), usg));
+                dbl = wq * (dblB + (C(1) + dblB) * poly2(dotc<L>(q, clB), usl));
+            } else {
+                const int xs = wrap_axis(x - L::c[q][0], p.nx, p.per[0]);
+                const int ys = wrap_axis(y - L::c[q][1], p.ny, p.per[1]);
+                const int zs = wrap_axis(z - L::c[q][2], p.nz, p.per[2]);
+                const long long src = ((long long)zs * p.ny + ys) * p.nx + xs;
+                C as, als, du[D];
+                if constexpr (INIT) {
+                    as = C(b.stage[src]);
+                    als = C(1) - as;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) du[a] = C(b.stage[(1 + a) * n + src] - b.stage[(1 + D + a) * n + src]);
+                } else {
+                    as = cfin[src];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) du[a] = cfin[(1 + a) * n + src];
+                    als = p.renorm ? C(1) - as : cfin[(1 + D) * n + src];
+                }
+                C cg[D], cl[D], usg = C(0), usl = C(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    cg[a] = als * du[a];
+                    cl[a] = as * (-du[a]);
+                    usg += cg[a] * cg[a];
+                    usl += cl[a] * cl[a];
+                }
+                dbg = wq * poly2(dotc<L>(q, cg), usg);
+                dbl = wq * poly2(dotc<L>(q, cl), usl);
+            }
+            Sg -= dbg;
+            Sl -= dbl;
+        }
+
+        if (ctl.write_diag) {
+            int bad = 0;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) bad += !isfinite(f[s][q]);
+            bad += !isfinite(Sg) + !isfinite(Sl);
+            dsum[16] = double(bad);
+        }
+
+        // ------------------------------------------------------- moments
+        C deg = C(0), del = C(0), ag = C(0), dal = C(0);
+        C ug[D], ul[D], Jg[D], Jl[D], Pg[NPI], Pl[NPI];
+#pragma unroll
+        for (int a = 0; a < D; ++a) ug[a] = ul[a] = Jg[a] = Jl[a] = C(0);
+#pragma unroll
+        for (int k = 0; k < NPI; ++k) Pg[k] = Pl[k] = C(0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            deg += f[0][q];  // Eq. (40), deviation from 1
+            del += f[1][q];
+            ag += f[2][q];   // Eq. (73)
+            dal += f[3][q];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int ca = L::c[q][a];
+                if (ca != 0) {  // Eqs. (41), (74)
+                    ug[a] += ca * f[0][q];
+                    ul[a] += ca * f[1][q];
+                    Jg[a] += ca * f[2][q];
+                    Jl[a] += ca * f[3][q];
+                }
+#pragma unroll
+                for (int bb = a; bb < D; ++bb) {
+                    const int cab = ca * L::c[q][bb];
+                    if (cab != 0) {  // second moment minus c_s^2 I
+                        Pg[sym<D>(a, bb)] += cab * f[0][q];
+                        Pl[sym<D>(a, bb)] += cab * f[1][q];
+                    }
+                }
+            }
+        }
+        // Pi - c_s^2 I from deviations: sum_q w_q v v = c_s^2 I
+        const C al_raw = C(1) + dal;
+
+        // ------------------------------- Spalding renormalisation, Eq. (93)
+        C alg, all, dall;
+        if (p.renorm) {
+            if (ag >= C(0) && ag <= C(1) && al_raw >= C(0) && al_raw <= C(1)) {
+                // B is the identity: alpha_g = a_g / (a_g + a_l), written around
+                // a_g + a_l = 1 so that FP32 keeps the small correction exactly
+                const C e = ag + dal;  // a_g + a_l - 1
+                alg = ag - ag * e / (C(1) + e);
+            } else {
+                const C Bg = clamp01(ag), Bl = clamp01(al_raw);
+                const C den = Bg + Bl;
+                alg = den > C(0) ? Bg / den : C(0);
+            }
+            all = C(1) - alg;
+            dall = -alg;
+        } else {
+            alg = ag;
+            all = al_raw;
+            dall = dal;
+        }
+
+        // ---------------------- sources, dashpots (Eqs. (128), (131)), lag
+        C usg = C(0), usl = C(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            usg += ug[a] * ug[a];
+            usl += ul[a] * ul[a];
+        }
+        const C R = C(p.R), invR = C(p.invR);
+        const C dphiel = deg * invR;  // phi eps_l - 1 = (eps_g - 1)/R, Eq. (32)
+        const C Spg = Sg - C(p.gamma) * usg * deg;
+        const C Spl = Sl - C(p.gamma) * usl * dphiel;
+        const C Lam = alg * all * (alg + all * R);  // Eq. (136)
+        C S2g = Spg, S2l = Spl, Laml = Lam;
+        if (p.use_lag) {
+            C* lag = static_cast<C*>(b.lag);
+            if (ctl.refresh) {
+                lag[node] = Spg;
+                lag[n + node] = Spl;
+                lag[2 * n + node] = Lam;
+            } else {
+                S2g = lag[node];
+                S2l = lag[n + node];
+                Laml = lag[2 * n + node];
+            }
+        }
+
+        // ---------------- volume-fraction gradient, Eqs. (91) and (94)
+        C grad[D];
+        const C og3 = C(3) * C(p.omega_ag), ol3 = C(3) * C(p.omega_al);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const C gg = og3 * (ag * ug[a] - Jg[a]);
+            const C gl = ol3 * (al_raw * ul[a] - Jl[a]);
+            grad[a] = C(0.5) * (gg - gl);  // grad alpha_g; grad alpha_l = -grad
+        }
+
+        // ------------------------------------------ stresses, Eq. (70)
+        C sg[NPI], sl[NPI];
+        {
+            const C kg = C(1) - C(0.5) * C(p.omega_g), kl = C(1) - C(0.5) * C(p.omega_l);
+            const C pg = third * C(p.psi_g) * C(0.5) * S2g, pl = third * C(p.psi_l) * C(0.5) * S2l;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+#pragma unroll
+                for (int bb = a; bb < D; ++bb) {
+                    const int k = sym<D>(a, bb);
+                    const C dg = a == bb ? third * deg : C(0);
+                    const C dl = a == bb ? third * dphiel : C(0);
+                    sg[k] = kg * (dg + ug[a] * ug[bb] - Pg[k]) - (a == bb ? pg : C(0));
+                    sl[k] = kl * (dl + ul[a] * ul[bb] - Pl[k]) - (a == bb ? pl : C(0));
+                }
+            }
+        }
+
+        // ------------------------------------------- forces, Eqs. (24), (26)
+        const C agf = alg > C(p.alpha_min) ? alg : C(p.alpha_min);
+        const C alf = all > C(p.alpha_min) ? all : C(p.alpha_min);
+        C du[D], dun2 = C(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            du[a] = ul[a] - ug[a];
+            dun2 += du[a] * du[a];
+        }
+        const C dun = sqrt(dun2);
+        const C uln = sqrt(usl);
+        const C K = p.cgw ? C(p.kappa_I) * Laml : C(p.K_I);
+        C Gg[D], Gl[D];
+        const C inv_agf = C(1) / agf, inv_alfR = C(1) / (alf * R);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            C sgg = C(0), sgl = C(0);
+            if (p.sigma_grad) {
+#pragma unroll
+                for (int bb = 0; bb < D; ++bb) {
+                    sgg += sg[sym<D>(a, bb)] * grad[bb];
+                    sgl -= sl[sym<D>(a, bb)] * grad[bb];
+                }
+                sgg = sgg * inv_agf;
+                sgl = sgl / alf;
+            }
+            const C bg = a == p.up ? C(p.b_g) : C(0);
+            const C bl = a == p.up ? C(p.b_l) : C(0);
+            Gg[a] = S2g * ug[a] + sgg + bg + K * dun * du[a] * inv_agf;
+            Gl[a] = S2l * ul[a] + sgl + bl + (-K * dun * du[a] - C(p.K_W) * uln * ul[a]) * inv_alfR;
+        }
+
+        // ---------------------------------------------------- collisions
+        T* pout = static_cast<T*>(b.pop_out);
+        {
+            const C w0 = C(L::w[0]);
+            const C k0 = (C(1) - w0) / w0;
+            const C el0 = del + k0 * (del - dphiel);  // eps_l eta_0(phi) - 1, Eq. (38)
+            const C eg0 = C(1) + k0 * (C(1) - C(p.psi_g));
+            const C el0p = C(1) + k0 * (C(1) - C(p.psi_l));
+            const C og = C(p.omega_g), ol = C(p.omega_l), oag = C(p.omega_ag), oal = C(p.omega_al);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const C wq = C(L::w[q]);
+                const C cug = dotc<L>(q, ug), cul = dotc<L>(q, ul);
+                const C cGg = dotc<L>(q, Gg), cGl = dotc<L>(q, Gl);
+                const C pg = poly2(cug, usg), pl = poly2(cul, usl);
+                const C feqg = wq * (deg + pg);                               // Eq. (37), phi = 1
+                const C feql = wq * ((q == 0 ? el0 : dphiel) + pl);           // Eq. (37), phi of Eq. (32)
+                const C fLg = wq * (S2g * (q == 0 ? eg0 : C(p.psi_g)) + C(3) * cGg);  // Eq. (42)
+                const C fLl = wq * (S2l * (q == 0 ? el0p : C(p.psi_l)) + C(3) * cGl);
+                const C feqa = wq * alg * (C(1) + pg);                        // Eq. (72)
+                const C feqb = wq * (dall + all * pl);
+                const C o0 = f[0][q] + og * (feqg - f[0][q]) + fLg;
+                const C o1 = f[1][q] + ol * (feql - f[1][q]) + fLl;
+                const C o2 = f[2][q] + oag * (feqa - f[2][q]);
+                const C o3 = f[3][q] + oal * (feqb - f[3][q]);
+                S::st(pout + (long long)(0 * Q + q) * n + node, o0);
+                S::st(pout + (long long)(1 * Q + q) * n + node, o1);
+                S::st(pout + (long long)(2 * Q + q) * n + node, o2);
+                S::st(pout + (long long)(3 * Q + q) * n + node, o3);
+            }
+        }
+
+        // ------------- imposed-velocity fields of the source schemes (Eq. (97))
+        {
+            C* cf = static_cast<C*>(b.cf_out);
+            cf[node] = alg;
+#pragma unroll
+            for (int a = 0; a < D; ++a) cf[(1 + a) * n + node] = ug[a] - ul[a];
+            if (!p.renorm) cf[(1 + D) * n + node] = all;
+        }
+
+        // -------------------- side buffers for the next step's face values
+        if constexpr (CH) {
+            if (fa >= 0) {
+                const int cf = co[fa];
+                int side = -1, layer = 0;
+                const bool lo_open = p.face_lo == EELBM_BC_INLET || p.face_lo == EELBM_BC_OUTLET;
+                const bool hi_open = p.face_hi == EELBM_BC_INLET || p.face_hi == EELBM_BC_OUTLET;
+                if (lo_open && cf <= 1) {
+                    side = 0;
+                    layer = cf;
+                }
+                if (hi_open && cf >= nn[fa] - 2) {
+                    if (side < 0 || cf == nn[fa] - 1) {
+                        side = 1;
+                        layer = nn[fa] - 1 - cf;
+                    }
+                }
+                if (side >= 0) {
+                    C* so = static_cast<C*>(b.side_out);
+                    auto put = [&](int v, C val) {
+                        so[((long long)(side * 2 + layer) * NV + v) * p.face_n + fidx] = val;
+                    };
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        put(a, ug[a]);
+                        put(D + a, ul[a]);
+                    }
+                    put(2 * D, alg);
+                    put(2 * D + 1, all);
+                    put(2 * D + 2, Sg);
+                    put(2 * D + 3, Sl);
+                }
+            }
+        }
+
+        // ------------------------------------------------ output fields
+        if (ctl.write_macro) {
+            double* m = b.macro;
+            m[node] = double(alg);
+            m[n + node] = double(all);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                m[(2 + a) * n + node] = double(ug[a]);
+                m[(2 + D + a) * n + node] = double(ul[a]);
+            }
+            m[(2 + 2 * D) * n + node] = double(deg) / 3.0;
+        }
+        if (ctl.write_diag) {
+            dsum[0] = double(ag);
+            dsum[1] = double(al_raw);
+            dsum[2] = double(alg);
+            dsum[3] = double(all);
+            dsum[4] = double(deg);
+            dsum[5] = double(del);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                dsum[6 + a] = double(ug[a]);
+                dsum[9 + a] = double(ul[a]);
+                dsum[12 + a] = p.rho_g * double(alg) * double(ug[a]) + p.rho_l * double(all) * double(ul[a]);
+            }
+            dsum[15] = double(alg) - double(ag);
+        }
+    }
+
+    // ---------------- FP64 wavefront -> block reduction of the diagnostics
+    if (ctl.write_diag) {
+        __shared__ double red[kNDiag][4];
+        // block sizes are whole wavefronts (checked on the host)
+        const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+        for (int k = 0; k < kNDiag; ++k) {
+            double v = dsum[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) red[k][wave] = v;
+        }
+        __syncthreads();
+        if (tid < kNDiag) {
+            const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+            double v = 0.0;
+            for (int w = 0; w < nw; ++w) v += red[tid][w];
+            b.partials[(long long)blockIdx.x * kNDiag + tid] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------- small reductions
+__global__ void __launch_bounds__(256) k_block_sum(const double* x, long long n, double* partials) {
+    __shared__ double red[256];
+    double v = 0.0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        v += x[i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// column sums of a [nrows][ncols] array in a fixed order (deterministic)
+__global__ void __launch_bounds__(256) k_col_sum(const double* a, int nrows, int ncols, double* out) {
+    __shared__ double red[256];
+    for (int c = 0; c < ncols; ++c) {
+        double v = 0.0;
+        for (int r = threadIdx.x; r < nrows; r += blockDim.x) v += a[(long long)r * ncols + c];
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[c] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_convert(const double* src, void* dst, int dtype, long long n, double add,
+                                                 double scale) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const double v = src[i] * scale + add;
+        if (dtype == EELBM_DTYPE_F64)
+            static_cast<double*>(dst)[i] = v;
+        else
+            static_cast<float*>(dst)[i] = float(v);
+    }
+}
+
+// ------------------------------------------------------------ launchers
+template <class L, class T, bool CH, bool INIT>
+static hipError_t go(const KParams& p, const KBuffers& b, const KCtl& c, dim3 g, dim3 bl, hipStream_t s) {
+    hipLaunchKernelGGL((k_step<L, T, CH, INIT>), g, bl, 0, s, p, b, c);
+    return hipGetLastError();
+}
+
+template <class L, class T>
+static hipError_t go2(bool ch, bool init, const KParams& p, const KBuffers& b, const KCtl& c, dim3 g, dim3 bl,
+                      hipStream_t s) {
+    if (ch) return init ? go<L, T, true, true>(p, b, c, g, bl, s) : go<L, T, true, false>(p, b, c, g, bl, s);
+    return init ? go<L, T, false, true>(p, b, c, g, bl, s) : go<L, T, false, false>(p, b, c, g, bl, s);
+}
+
+template <class L>
+static hipError_t go1(int storage, bool ch, bool init, const KParams& p, const KBuffers& b, const KCtl& c, dim3 g,
+                      dim3 bl, hipStream_t s) {
+    switch (storage) {
+        case EELBM_FP64: return go2<L, double>(ch, init, p, b, c, g, bl, s);
+        case EELBM_FP32: return go2<L, float>(ch, init, p, b, c, g, bl, s);
+        case EELBM_FP16: return go2<L, __half>(ch, init, p, b, c, g, bl, s);
+        case EELBM_BF16: return go2<L, __hip_bfloat16>(ch, init, p, b, c, g, bl, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_step(int lattice, int storage, bool channel, bool init, const KParams& p, const KBuffers& b,
+                       const KCtl& c, dim3 grid, dim3 block, hipStream_t s) {
+    if (lattice == EELBM_D2Q9) return go1<D2Q9>(storage, channel, init, p, b, c, grid, block, s);
+    if (lattice == EELBM_D3Q19) return go1<D3Q19>(storage, channel, init, p, b, c, grid, block, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sum(const double* x, long long n, double* partials, int nblocks, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_block_sum, dim3(nblocks), dim3(256), 0, s, x, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(256), 0, s, partials, nblocks, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_finalize(const double* partials, int nblocks, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(256), 0, s, partials, nblocks, kNDiag, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const double* src, void* dst, int dst_dtype, long long n, double add, double scale,
+                          hipStream_t s) {
+    long long blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_convert, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, dst_dtype, n, add, scale);
+    return hipGetLastError();
+}
+
+}  // namespace eelbm

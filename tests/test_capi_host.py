@@ -1,0 +1,70 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every function include/eelbm.h declares, mirrors its structs, validates
+parameters and maps physical units as Sec. 3.3 prescribes."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2409_10399_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libeelbm.so is not built (run python -m paper_2409_10399_amd.build)")
+    return binding
+
+
+def test_library_exports_every_declared_symbol():
+    b = _lib()
+    header = open(os.path.join(ROOT, "include", "eelbm.h")).read()
+    names = set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(eelbm_\w+)\s*\(", header, flags=re.M))
+    assert len(names) >= 14
+    L = ctypes.CDLL(b.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert set(b.SYMBOLS) == names
+
+
+def test_struct_mirror_and_version():
+    b = _lib()
+    L = b.lib()
+    assert L.eelbm_abi_version() == b.ABI_VERSION
+    assert L.eelbm_params_size() == ctypes.sizeof(b.Params)
+
+
+def test_state_bytes_and_validation():
+    b = _lib()
+    cfg, _ = workloads.channel_2d()
+    n = 1024 * 1024
+    nb = b.state_bytes(cfg, "fp32")
+    assert nb >= 2 * 4 * 9 * 4 * n + 2 * 4 * 4 * n
+    assert b.state_bytes(cfg, "fp16") < nb < b.state_bytes(cfg, "fp64")
+    bad = [dict(omega_g=2.0), dict(omega_al=0.0), dict(rho_g=0.0), dict(n_gamma=0), dict(alpha_min=0.0),
+           dict(up_axis=2), dict(bc={"x-": "wall", "x+": "periodic"}),
+           dict(bc={"x-": "inlet", "x+": "outlet", "y-": "inlet", "y+": "outlet"}), dict(ny=3)]
+    for kw in bad:
+        c = dict(cfg)
+        c.update(kw)
+        with pytest.raises(b.EelbmError) as e:
+            b.state_bytes(c)
+        assert e.value.code == -1, kw
+    c3 = workloads._base("D3Q19", nx=8, ny=8, nz=8)
+    assert b.state_bytes(c3, "fp32") > 0
+
+
+def test_map_physical_reproduces_test4_numbers():
+    b = _lib()
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "test4_mapping.json")))
+    i, pr = g["inputs"], g["printed"]
+    m = b.map_physical(i["g"], i["kappa_I"], i["g_hat"], i["kappa_hat"])
+    assert abs(m["c_over_tau"] / pr["c_over_tau"] - 1) < 1e-3
+    assert abs(m["c_tau"] / pr["c_tau"] - 1) < 1e-3
+    assert abs(m["c"] / pr["c"] - 1) < 1e-3
+    with pytest.raises(b.EelbmError):
+        b.map_physical(-1.0, 1.0, 1.0, 1.0)
