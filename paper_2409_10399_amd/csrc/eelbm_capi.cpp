@@ -61,7 +61,7 @@ void set_tiles(const eelbm_params& p, Geometry* g, int bx, int by, int xcd) {
         bx = env_int("EELBM_TILE_X", 0);
         by = env_int("EELBM_TILE_Y", 0);
     }
-    if (bx <= 0 || by <= 0 || bx * by > 256 || (bx * by) % 64 != 0) {
+    if (bx <= 0 || by <= 0 || bx % 64 != 0 || bx * by > 256) {
         bx = ((p.nx + 63) / 64) * 64;
         if (bx > 256) bx = 256;
         by = 1;
@@ -88,7 +88,16 @@ int validate(const eelbm_params* pp, Geometry* g) {
     if (D == 2 && p.nz != 1) return fail(EELBM_E_PARAM, "D2Q9 needs nz = 1");
     if (p.ny > 65535 || p.nz > 65535) return fail(EELBM_E_PARAM, "ny and nz must be <= 65535");
     const long long n = (long long)p.nx * p.ny * p.nz;
-    if (n > (1LL << 31) / 4) return fail(EELBM_E_PARAM, "too many nodes for one lattice");
+    // every per-node array (the widest: 4-wide FP64 records) stays below 4 GiB,
+    // so kernels address it with 32-bit byte offsets
+    if ((unsigned long long)n * 4 * (p.storage == EELBM_FP64 ? 8 : 4) >= (1ull << 32))
+        return fail(EELBM_E_PARAM, "too many nodes for one lattice");
+    // ... and so does one z-plane of a population copy (buffer descriptors)
+    {
+        const unsigned long long tsz = p.storage == EELBM_FP64 ? 8 : (p.storage == EELBM_FP32 ? 4 : 2);
+        const unsigned long long plane = (unsigned long long)p.ny * ((p.nx + 63) / 64) * 64 * 4 * (D == 2 ? 9 : 19);
+        if (plane * tsz >= (1ull << 32)) return fail(EELBM_E_PARAM, "lattice plane too large");
+    }
     int flow_axis = -1;
     const int nn[3] = {p.nx, p.ny, p.nz};
     for (int a = 0; a < 3; ++a) {
@@ -145,6 +154,25 @@ size_t max_blocks(const eelbm_params& p) {
     return ((size_t)p.nx * p.ny / 64 + p.nx + p.ny + 2) * (size_t)p.nz;
 }
 
+// population copy: per z-plane, rows of 64-node x-blocks, each block holding
+// its 4Q populations contiguously (the layout the step kernel reads)
+int x_blocks(const eelbm_params& p) { return (p.nx + 63) / 64; }
+size_t pop_plane_elems(const eelbm_params& p, const Geometry& g) {
+    return (size_t)p.ny * x_blocks(p) * 4 * g.Q * 64;
+}
+size_t pop_bytes(const eelbm_params& p, const Geometry& g) { return (size_t)p.nz * pop_plane_elems(p, g) * g.tsize; }
+
+// imposed-velocity region of one ping-pong copy: [n] 4-wide records, then
+// [n] alpha_l values (used only without renormalisation)
+size_t cf_records_bytes(const Geometry& g) { return align256(4 * (size_t)g.n * g.csize); }
+size_t cf_region_bytes(const Geometry& g) { return cf_records_bytes(g) + (size_t)g.n * g.csize; }
+// lag region: [n] 2-wide records (S''_g, S''_l), then [n] Lambda' in 3D
+size_t lag_records_bytes(const Geometry& g) { return align256(2 * (size_t)g.n * g.csize); }
+size_t lag_region_bytes(const eelbm_params& p, const Geometry& g) {
+    if (p.n_gamma <= 1) return 0;
+    return lag_records_bytes(g) + (g.D == 3 ? (size_t)g.n * g.csize : 0);
+}
+
 Layout layout(const eelbm_params& p, const Geometry& g) {
     Layout L{};
     size_t off = 0;
@@ -155,9 +183,9 @@ Layout layout(const eelbm_params& p, const Geometry& g) {
     };
     const size_t n = (size_t)g.n;
     const int NV = 2 * g.D + 4;
-    for (int k = 0; k < 2; ++k) L.pop[k] = take(4 * (size_t)g.Q * n * g.tsize);
-    for (int k = 0; k < 2; ++k) L.cf[k] = take((size_t)(2 + g.D) * n * g.csize);
-    L.lag = take(p.n_gamma > 1 ? 3 * n * g.csize : 0);
+    for (int k = 0; k < 2; ++k) L.pop[k] = take(pop_bytes(p, g));
+    for (int k = 0; k < 2; ++k) L.cf[k] = take(cf_region_bytes(g));
+    L.lag = take(lag_region_bytes(p, g));
     for (int k = 0; k < 2; ++k) L.side[k] = take((size_t)2 * 2 * NV * (size_t)g.face_n * g.csize);
     L.noise = take((size_t)g.face_n * 8);
     L.stage = take((size_t)(2 + 2 * g.D) * n * 8);
@@ -188,6 +216,8 @@ struct eelbm_handle {
     int cur;
     bool initialized;
     double rho_ref, b_g, b_l;
+    double alpha_ref;  // mean initial gas fraction: reference of the f_alpha deviations
+    int64_t diag_blocks;  // workgroups that wrote the current diagnostic partial sums
     KParams kp;
 };
 
@@ -200,7 +230,10 @@ KBuffers buffers(eelbm_handle* h, int in, int out) {
     b.pop_out = m + h->L.pop[out];
     b.cf_in = m + h->L.cf[in];
     b.cf_out = m + h->L.cf[out];
+    b.al_in = m + h->L.cf[in] + cf_records_bytes(h->g);
+    b.al_out = m + h->L.cf[out] + cf_records_bytes(h->g);
     b.lag = m + h->L.lag;
+    b.lag_lam = m + h->L.lag + lag_records_bytes(h->g);
     b.side_in = m + h->L.side[in];
     b.side_out = m + h->L.side[out];
     b.noise = reinterpret_cast<const double*>(m + h->L.noise);
@@ -219,6 +252,8 @@ void fill_kparams(eelbm_handle* h) {
     k.nz = p.nz;
     k.n = h->g.n;
     k.ntx = h->g.ntx;
+    k.nxb = x_blocks(p);
+    k.plane = (long long)pop_plane_elems(p, h->g);
     k.nty = h->g.nty;
     k.xcd_remap = h->g.xcd_remap;
     for (int a = 0; a < 3; ++a) {
@@ -252,6 +287,7 @@ void fill_kparams(eelbm_handle* h) {
     k.b_l = h->b_l;
     k.gamma = p.gamma;
     k.alpha_min = p.alpha_min;
+    k.alpha_ref = h->alpha_ref;
 }
 
 int launch(eelbm_handle* h, bool init, int64_t t, bool last) {
@@ -270,6 +306,7 @@ int launch(eelbm_handle* h, bool init, int64_t t, bool last) {
     hipError_t e = launch_step(h->p.lattice, h->p.storage, h->g.channel, init, h->kp, b, c, h->g.grid, h->g.block,
                                h->stream);
     if (e != hipSuccess) return hip_fail(e, "k_step launch");
+    if (last) h->diag_blocks = h->g.nblocks;
     h->cur = out;
     h->t = t;
     return EELBM_OK;
@@ -368,13 +405,11 @@ int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g,
         }
         if (rc) return rc;
     }
-    // buoyancy reference density
+    // mean initial gas fraction: reference of the f_alpha deviations and,
+    // for EELBM_RHOREF_MIXTURE_MEAN, of the buoyancy reference density
     const eelbm_params& p = h->p;
-    if (p.rho_ref_mode == EELBM_RHOREF_LIQUID) {
-        h->rho_ref = p.rho_l;
-    } else if (p.rho_ref_mode == EELBM_RHOREF_EXPLICIT) {
-        h->rho_ref = p.rho_ref;
-    } else {
+    double am = 0.0;
+    {
         double* sp = reinterpret_cast<double*>(h->mem + h->L.spart);
         double* so = reinterpret_cast<double*>(h->mem + h->L.dout) + kNDiag;
         e = launch_sum(stage, (long long)n, sp, 1024, so, h->stream);
@@ -383,7 +418,15 @@ int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g,
         e = hipMemcpyAsync(&sum, so, 8, hipMemcpyDeviceToHost, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) return hip_fail(e, "alpha sum read-back");
-        const double am = sum / (double)n;
+        am = sum / (double)n;
+    }
+    if (!std::isfinite(am)) return fail(EELBM_E_NONFINITE, "non-finite initial gas fraction");
+    h->alpha_ref = p.storage == EELBM_FP64 ? am : (double)(float)am;
+    if (p.rho_ref_mode == EELBM_RHOREF_LIQUID) {
+        h->rho_ref = p.rho_l;
+    } else if (p.rho_ref_mode == EELBM_RHOREF_EXPLICIT) {
+        h->rho_ref = p.rho_ref;
+    } else {
         h->rho_ref = am * p.rho_g + (1.0 - am) * p.rho_l;
     }
     h->b_g = (h->rho_ref / p.rho_g - 1.0) * p.g_hat;
@@ -415,8 +458,8 @@ int64_t eelbm_time(const eelbm_handle* h) { return h ? h->t : -1; }
 
 int eelbm_set_launch(eelbm_handle* h, int32_t tile_x, int32_t tile_y, int32_t xcd_remap) {
     if (!h) return fail(EELBM_E_PARAM, "handle is NULL");
-    if (tile_x < 1 || tile_y < 1 || tile_x * tile_y > 256 || (tile_x * tile_y) % 64 != 0)
-        return fail(EELBM_E_PARAM, "tile must hold a whole number of 64-wide wavefronts, at most 256 nodes");
+    if (tile_x < 64 || tile_y < 1 || tile_x % 64 != 0 || tile_x * tile_y > 256)
+        return fail(EELBM_E_PARAM, "tile_x must be a multiple of 64 (one x-block per wavefront), at most 256 nodes");
     if (h->g.D == 2 && tile_y > h->p.ny) return fail(EELBM_E_PARAM, "tile_y exceeds ny");
     set_tiles(h->p, &h->g, tile_x, tile_y, xcd_remap ? 1 : 0);
     fill_kparams(h);
@@ -481,7 +524,7 @@ int eelbm_diag(eelbm_handle* h, eelbm_diagnostics* out) {
     if (!h->initialized) return fail(EELBM_E_STATE, "eelbm_init_fields not called");
     double* parts = reinterpret_cast<double*>(h->mem + h->L.partials);
     double* d = reinterpret_cast<double*>(h->mem + h->L.dout);
-    hipError_t e = launch_diag_finalize(parts, h->g.nblocks, d, h->stream);
+    hipError_t e = launch_diag_finalize(parts, (int)h->diag_blocks, d, h->stream);
     if (e != hipSuccess) return hip_fail(e, "diag launch");
     double v[kNDiag];
     e = hipMemcpyAsync(v, d, sizeof(v), hipMemcpyDeviceToHost, h->stream);
@@ -513,19 +556,20 @@ struct SaveHeader {
     uint64_t magic;
     int32_t abi, lattice, storage, nx, ny, nz;
     int64_t t;
-    double rho_ref, b_g, b_l;
+    double rho_ref, b_g, b_l, alpha_ref;
+    int64_t diag_blocks;
     uint64_t pop_bytes, cf_bytes, lag_bytes, side_bytes, macro_bytes, part_bytes, noise_bytes;
 };
 constexpr uint64_t kMagic = 0x45454c424d434b31ull;  // "EELBMCK1"
 
 void save_sizes(const eelbm_handle* h, SaveHeader* s) {
     const size_t n = (size_t)h->g.n;
-    s->pop_bytes = 4 * (size_t)h->g.Q * n * h->g.tsize;
-    s->cf_bytes = (size_t)(2 + h->g.D) * n * h->g.csize;
-    s->lag_bytes = h->p.n_gamma > 1 ? 3 * n * h->g.csize : 0;
+    s->pop_bytes = pop_bytes(h->p, h->g);
+    s->cf_bytes = cf_region_bytes(h->g);
+    s->lag_bytes = lag_region_bytes(h->p, h->g);
     s->side_bytes = (size_t)2 * 2 * (2 * h->g.D + 4) * (size_t)h->g.face_n * h->g.csize;
     s->macro_bytes = (size_t)(3 + 2 * h->g.D) * n * 8;
-    s->part_bytes = (size_t)h->g.nblocks * kNDiag * 8;
+    s->part_bytes = (size_t)h->diag_blocks * kNDiag * 8;
     s->noise_bytes = (size_t)h->g.face_n * 8;
 }
 }  // namespace
@@ -553,6 +597,8 @@ int eelbm_save(eelbm_handle* h, void* host_buf, size_t* bytes) {
     s.rho_ref = h->rho_ref;
     s.b_g = h->b_g;
     s.b_l = h->b_l;
+    s.alpha_ref = h->alpha_ref;
+    s.diag_blocks = h->diag_blocks;
     char* o = static_cast<char*>(host_buf);
     std::memcpy(o, &s, sizeof(s));
     o += sizeof(s);
@@ -578,7 +624,12 @@ int eelbm_load(eelbm_handle* h, const void* host_buf, size_t bytes) {
     SaveHeader s{}, want{};
     if (bytes < sizeof(s)) return fail(EELBM_E_SIZE, "checkpoint too small");
     std::memcpy(&s, host_buf, sizeof(s));
+    if (s.diag_blocks < 0 || (size_t)s.diag_blocks > max_blocks(h->p))
+        return fail(EELBM_E_PARAM, "checkpoint does not match this lattice");
+    const int64_t keep_blocks = h->diag_blocks;
+    h->diag_blocks = s.diag_blocks;
     save_sizes(h, &want);
+    h->diag_blocks = keep_blocks;
     if (s.magic != kMagic || s.abi != EELBM_ABI_VERSION || s.lattice != h->p.lattice || s.storage != h->p.storage ||
         s.nx != h->p.nx || s.ny != h->p.ny || s.nz != h->p.nz || s.pop_bytes != want.pop_bytes ||
         s.cf_bytes != want.cf_bytes || s.lag_bytes != want.lag_bytes || s.side_bytes != want.side_bytes ||
@@ -602,6 +653,8 @@ int eelbm_load(eelbm_handle* h, const void* host_buf, size_t bytes) {
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     h->t = s.t;
+    h->diag_blocks = s.diag_blocks;
+    h->alpha_ref = s.alpha_ref;
     h->rho_ref = s.rho_ref;
     h->b_g = s.b_g;
     h->b_l = s.b_l;

@@ -15,6 +15,8 @@ struct KParams {
     int nx, ny, nz;
     long long n;        // nodes
     int ntx, nty;       // tiles per plane along x and y (tile = blockDim.x * blockDim.y nodes)
+    int nxb;            // 64-node x-blocks per row of the population layout
+    long long plane;    // population elements of one z-plane (ny * nxb * 4Q * 64)
     int xcd_remap;      // map contiguous tile runs to one XCD
     int per[3];         // axis periodic?
     int wall_lo[3], wall_hi[3];
@@ -31,15 +33,19 @@ struct KParams {
     double K_I, kappa_I, K_W;
     double b_g, b_l;    // buoyancy accelerations along up
     double gamma, alpha_min;
+    double alpha_ref;   // reference of the f_alpha deviations (mean initial alpha_g)
 };
 
 // Device pointers of one launch (ping-pong halves already selected).
 struct KBuffers {
     const void* pop_in;   // [4][Q][n] storage type: deviations of f_g, f_l, f_ag, f_al
     void* pop_out;
-    const void* cf_in;    // [2 + D][n] compute type: alpha_g, du(D) = u_g - u_l, alpha_l
-    void* cf_out;
-    void* lag;            // [3][n] compute type: S''_g, S''_l, Lambda'
+    const void* cf_in;    // [n] records of 4 compute-type values: alpha_g, du(D) = u_g - u_l,
+    void* cf_out;         //     and Lambda' in the fourth slot of D2Q9
+    const void* al_in;    // [n] alpha_l (read and written only without renormalisation)
+    void* al_out;
+    void* lag;            // [n] records of 2: S''_g, S''_l
+    void* lag_lam;        // [n] Lambda' (D3Q19 only)
     const void* side_in;  // [2 faces][2 layers][NV][face_n] compute type
     void* side_out;
     const double* noise;  // [face_n] inlet gas-fraction factor

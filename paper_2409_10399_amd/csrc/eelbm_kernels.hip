@@ -12,16 +12,24 @@
 // populations (coalesced stores, SoA, x fastest).
 //
 // State kept between launches, per node:
-//  * f_g, f_l, f_ag, f_al post-collision, as deviations from w_q (w_q * 0 for
-//    f_ag), in the storage type;
-//  * (alpha_g, u_g - u_l) -- the post-collision f_b of the lattice kinetic
-//    scheme is the pure function f^eq(1, c_phi) of these (Eqs. (95), (97) with
+//  * f_g, f_l as deviations from w_q, f_ag, f_al as deviations from
+//    w_q alpha_r and w_q (1 - alpha_r) (alpha_r: the mean initial gas
+//    fraction), post-collision, in the storage type;
+//  * one 4-wide record (alpha_g, u_g - u_l, and Lambda' in the free slot of
+//    D2Q9): the post-collision f_b of the lattice kinetic scheme is the pure
+//    function f^eq(1, c_phi) of alpha_g and u_g - u_l (Eqs. (95), (97) with
 //    beta = 1), so f_b is rebuilt at the gather from the upstream node's
-//    values instead of being stored: 1 + D numbers instead of 2Q;
-//  * the lag fields S''_g, S''_l, Lambda' when n_gamma > 1;
+//    record instead of being stored -- 1 + D numbers instead of 2Q, read
+//    with one 16-byte load per upstream node;
+//  * the lag fields S''_g, S''_l (and Lambda' in 3D) when n_gamma > 1;
 //  * for the two node layers next to an inlet/outlet face, the macroscopic
 //    values the boundary extrapolations of Eqs. (160)-(161) need at the next
 //    step (u_g, u_l, alpha_g, alpha_l, S_g, S_l).
+//
+// Wavefronts whose nodes all pull from interior neighbours take a fast
+// gather: every load is a wave-uniform base plus one shared 32-bit node
+// offset.  Wavefronts touching a face (periodic wrap or a boundary rule) take
+// the general gather.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -32,11 +40,14 @@
 
 namespace eelbm {
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------- storage
 template <class T>
 struct Store;
 // Populations are read exactly once per step: they are loaded nontemporally
-// so that they do not displace the imposed-velocity fields (read by nine
+// so that they do not displace the imposed-velocity records (read by nine
 // nodes) and the freshly written populations, which the next step reads back,
 // from L2 and the Infinity Cache.  Stores stay ordinary (measured: nontemporal
 // stores, or nontemporal loads of the lag fields, are slower on gfx950).
@@ -70,6 +81,103 @@ struct Store<__hip_bfloat16> {
     static __device__ __forceinline__ void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
 };
 
+// 4-wide imposed-velocity record and 2-wide lag record (one vector load each)
+template <class C>
+struct alignas(4 * sizeof(C)) Rec4 {
+    C v[4];
+};
+template <class C>
+struct alignas(2 * sizeof(C)) Rec2 {
+    C v[2];
+};
+
+__device__ __forceinline__ Rec4<float> ld_rec(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float) {
+    return __builtin_bit_cast(Rec4<float>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ Rec4<double> ld_rec(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double) {
+    struct Two {
+        u32x4 a, b;
+    } t;
+    t.a = __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0);
+    t.b = __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)(so + 16), 0);
+    return __builtin_bit_cast(Rec4<double>, t);
+}
+__device__ __forceinline__ void st_rec(__amdgpu_buffer_rsrc_t r, unsigned vo, const Rec4<float>& v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)vo, 0, 0);
+}
+__device__ __forceinline__ void st_rec(__amdgpu_buffer_rsrc_t r, unsigned vo, const Rec4<double>& v) {
+    struct Two {
+        u32x4 a, b;
+    };
+    const Two t = __builtin_bit_cast(Two, v);
+    __builtin_amdgcn_raw_buffer_store_b128(t.a, r, (int)vo, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(t.b, r, (int)vo, 16, 0);
+}
+
+// ------------------------------------------------- buffer-instruction I/O
+// The hot streams use buffer instructions: a descriptor in SGPRs, one VGPR
+// byte offset shared by every access of a node, and the per-direction shift
+// in an SGPR offset, so an access costs no vector ALU work.  Bit 1 of the
+// cache-policy operand is the nontemporal hint on gfx950.
+constexpr int kNT = 2;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
+}
+
+template <class T>
+struct Buf;
+template <>
+struct Buf<float> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, kNT));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)vo, (int)so, 0);
+    }
+};
+template <>
+struct Buf<double> {
+    static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, kNT));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vo, (int)so, 0);
+    }
+};
+template <>
+struct Buf<__half> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, kNT)));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, (int)vo, (int)so, 0);
+    }
+};
+template <>
+struct Buf<__hip_bfloat16> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        const unsigned short bits = __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, kNT);
+        return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, bits));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2bfloat16(v)), r, (int)vo,
+                                              (int)so, 0);
+    }
+};
+
+// wave-uniform base + 32-bit per-lane byte offset: compiles to a global
+// load/store with an SGPR base, one shared VGPR offset and an immediate
+// (the host keeps every array below 4 GiB)
+template <class X>
+__device__ __forceinline__ const X* at(const X* base, unsigned byte_off) {
+    return reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <class X>
+__device__ __forceinline__ X* at(X* base, unsigned byte_off) {
+    return reinterpret_cast<X*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
 template <class C>
 __device__ __forceinline__ C clamp01(C v) {
     return v < C(0) ? C(0) : (v > C(1) ? C(1) : v);
@@ -99,20 +207,41 @@ __device__ __forceinline__ int wrap_axis(int v, int nax, int per) {
     return v;
 }
 
+// source-scheme population deviations of one upstream node: w_q-normalised
+// f^eq(1, c) - w_q with c_g = alpha_l du, c_l = -alpha_g du (Eqs. (72), (97))
+template <class L, class C>
+__device__ __forceinline__ void beta_dev(int q, C as, C als, const C* du, C& dbg, C& dbl) {
+    constexpr int D = L::D;
+    C vd = C(0), dd = C(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) dd += du[a] * du[a];
+    vd = dotc<L>(q, du);
+    const C even = C(4.5) * vd * vd - C(1.5) * dd;
+    const C wq = C(L::w[q]);
+    dbg = wq * als * (C(3) * vd + als * even);
+    dbl = wq * as * (-C(3) * vd + as * even);
+}
+
+// Population layout: each z-plane is a sequence of x-blocks of 64 nodes (rows
+// padded to a whole number of blocks); one block holds the 4Q post-collision
+// populations of its 64 nodes contiguously, [set * Q + q][lane].  A wavefront
+// (64 nodes of one block) therefore reads a few contiguous regions and writes
+// one, instead of touching 4Q separate streams (DRAM row locality).
+template <int Q>
+__device__ __forceinline__ long long pop_index(const KParams& p, int x, int y, int z, int sq) {
+    return (long long)z * p.plane + (((long long)y * p.nxb + (x >> 6)) * (4 * Q * 64) + sq * 64 + (x & 63));
+}
+
 // --------------------------------------------------------------- the step
-#ifdef EELBM_WAVES_PER_EU
-#define EELBM_WPE __attribute__((amdgpu_waves_per_eu(EELBM_WAVES_PER_EU)))
-#else
-#define EELBM_WPE
-#endif
 template <class L, class T, bool CH, bool INIT>
-__global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const KBuffers b, const KCtl ctl) {
+__global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b, const KCtl ctl) {
     using C = typename Store<T>::C;
     using S = Store<T>;
     constexpr int D = L::D;
     constexpr int Q = L::Q;
     constexpr int NPI = L::NPI;
     constexpr int NV = 2 * D + 4;  // side-buffer values per node
+    constexpr int kBlk = 4 * Q * 64;  // population elements of one x-block
     const C third = C(1) / C(3);
 
     // Tiles of blockDim.x * blockDim.y nodes in an (x, y) plane, one grid
@@ -134,8 +263,12 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
     const bool act = x < p.nx && y < p.ny;
     const long long n = p.n;
     const long long node = ((long long)z * p.ny + y) * p.nx + x;
+    const unsigned tb = (unsigned)node * (unsigned)sizeof(T);         // byte offset in a population array
+    const unsigned rb = (unsigned)node * (unsigned)sizeof(Rec4<C>);   // ... in the record array
+    const unsigned cb = (unsigned)node * (unsigned)sizeof(C);         // ... in a scalar array
     const int co[3] = {x, y, z};
     const int nn[3] = {p.nx, p.ny, p.nz};
+    const long long nxy = (long long)p.nx * p.ny;
 
     double dsum[kNDiag];
 #pragma unroll
@@ -143,8 +276,16 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
 
     if (act) {
         const T* pin = static_cast<const T*>(b.pop_in);
-        const C* cfin = static_cast<const C*>(b.cf_in);
+        const Rec4<C>* cfin = static_cast<const Rec4<C>*>(b.cf_in);
+        const C* alin = static_cast<const C*>(b.al_in);
         const C* sidein = static_cast<const C*>(b.side_in);
+        const C ar = C(p.alpha_ref);
+
+        // a lane whose pulls wrap around a periodic face or cross a boundary
+        bool fix = false;
+#pragma unroll
+        for (int a = 0; a < D; ++a) fix = fix || co[a] == 0 || co[a] == nn[a] - 1;
+        const bool general = INIT || __any(fix);
 
         // -------------------------------------------------- boundary layout
         bool lo[3] = {false, false, false}, hi[3] = {false, false, false};
@@ -152,7 +293,7 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
         int fs = -1;            // flow-axis face this node lies on (0 low, 1 high)
         int ftype = EELBM_BC_PERIODIC;
         long long fidx = 0;     // node index within that face
-        int fa = p.flow_axis;
+        const int fa = p.flow_axis;
         if constexpr (CH) {
 #pragma unroll
             for (int a = 0; a < D; ++a) {
@@ -175,7 +316,7 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
 
         // values on the flow face (Sec. 3.5, STEP #1)
         C uinG[D], uinL[D], ain = C(0);                 // inlet: imposed u and alpha
-        C ugB[D], ulB[D], agB = C(0), dalB = C(0);      // outlet: EX(hw)
+        C ugB[D], ulB[D], agB = C(0), alB = C(0);       // outlet: EX(hw)
         C cgB[D], clB[D], dbgB = C(0), dblB = C(0);     // beta, c: EX(fw); db = beta - 1
 #pragma unroll
         for (int a = 0; a < D; ++a) uinG[a] = uinL[a] = ugB[a] = ulB[a] = cgB[a] = clB[a] = C(0);
@@ -193,9 +334,8 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
                 if constexpr (INIT) {
                     // t = -1: beta = 1, c from the initial fields of the edge
                     // node and its inward neighbour
-                    long long e = node, nx1 = node;
-                    const long long st = fa == 0 ? 1 : (fa == 1 ? (long long)p.nx : (long long)p.nx * p.ny);
-                    nx1 = fs == 0 ? node + st : node - st;
+                    const long long st = fa == 0 ? 1 : (fa == 1 ? (long long)p.nx : nxy);
+                    const long long e = node, nx1 = fs == 0 ? node + st : node - st;
                     const double ae = b.stage[e], an = b.stage[nx1];
 #pragma unroll
                     for (int a = 0; a < D; ++a) {
@@ -220,7 +360,7 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
                         clB[a] = C(2) * (ae * (ule - uge)) - an * (uln - ugn);
                     }
                     agB = C(1.5) * ae - C(0.5) * an;
-                    dalB = p.renorm ? -agB : (C(1.5) * ale - C(0.5) * aln) - C(1);
+                    alB = p.renorm ? C(1) - agB : C(1.5) * ale - C(0.5) * aln;
                     // beta - 1 = -S, extrapolated full-way
                     dbgB = -(C(2) * sv(0, 2 * D + 2) - sv(1, 2 * D + 2));
                     dblB = -(C(2) * sv(0, 2 * D + 3) - sv(1, 2 * D + 3));
@@ -255,8 +395,35 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
                 const C el = q == 0 ? -k0 * de0 * C(p.invR) : de0 * C(p.invR);
                 f[0][q] = wq * (de0 + poly2(cug, us0g));
                 f[1][q] = wq * (el + poly2(cul, us0l));
-                f[2][q] = wq * a0 * (C(1) + poly2(cug, us0g));
-                f[3][q] = wq * (-a0 + (C(1) - a0) * poly2(cul, us0l));
+                f[2][q] = wq * ((a0 - ar) + a0 * poly2(cug, us0g));
+                f[3][q] = wq * ((ar - a0) + (C(1) - a0) * poly2(cul, us0l));
+            }
+        } else if (!general) {
+            // Interior wavefront (64 lanes = one x-block, see pop_index): the
+            // source of direction q lies in x-block xb of row y - c_y (plane
+            // z - c_z), or in its neighbour block for the lane at the block
+            // edge.  The wave-uniform part, taken from block xb - 1, goes in
+            // the SGPR offset; the three per-lane parts (one per c_x) are
+            // computed once.
+            const int xb = x >> 6, xl = x & 63;
+            unsigned vo[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int src = xl - (k - 1);
+                vo[k] = (unsigned)((src < 0 ? 63 : (src > 63 ? 2 * kBlk : kBlk + src)) * (int)sizeof(T));
+            }
+            __amdgpu_buffer_rsrc_t rp[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (D == 3 || k == 1) rp[k] = rsrc(pin + (long long)(z - (k - 1)) * p.plane);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const long long blk = (long long)(y - L::c[q][1]) * p.nxb + (xb - 1);
+                    const unsigned so = (unsigned)((blk * kBlk + (s * Q + q) * 64) * (long long)sizeof(T));
+                    f[s][q] = Buf<T>::ld(rp[L::c[q][2] + 1], vo[L::c[q][0] + 1], so);
+                }
             }
         } else {
 #pragma unroll
@@ -264,9 +431,8 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
                 const int xs = wrap_axis(x - L::c[q][0], p.nx, p.per[0]);
                 const int ys = wrap_axis(y - L::c[q][1], p.ny, p.per[1]);
                 const int zs = wrap_axis(z - L::c[q][2], p.nz, p.per[2]);
-                const long long src = ((long long)zs * p.ny + ys) * p.nx + xs;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) f[s][q] = S::ld(pin + (long long)(s * Q + q) * n + src);
+                for (int s = 0; s < 4; ++s) f[s][q] = S::ld(pin + pop_index<Q>(p, xs, ys, zs, s * Q + q));
             }
             if constexpr (CH) {
                 if (edge) {
@@ -286,13 +452,13 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
                         const int qo = L::opp[q];
                         C fo[4];
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) fo[s] = S::ld(pin + (long long)(s * Q + qo) * n + node);
+                        for (int s = 0; s < 4; ++s) fo[s] = S::ld(pin + pop_index<Q>(p, x, y, z, s * Q + qo));
+                        const C wq = C(L::w[q]);
                         if (wall) {
                             // half-way bounce-back, zero wall velocity
 #pragma unroll
                             for (int s = 0; s < 4; ++s) f[s][q] = fo[s];
                         } else if (ftype == EELBM_BC_INLET) {
-                            const C wq = C(L::w[q]);
                             C usg = C(0), usl = C(0);
 #pragma unroll
                             for (int a = 0; a < D; ++a) {
@@ -304,10 +470,9 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
                             f[0][q] = fo[0] + C(6) * wq * cug;
                             f[1][q] = fo[1] + C(6) * wq * cul;
                             // EQ(S) with the imposed alpha and velocity
-                            f[2][q] = wq * ain * (C(1) + poly2(cug, usg));
-                            f[3][q] = wq * (-ain + (C(1) - ain) * poly2(cul, usl));
+                            f[2][q] = wq * ((ain - ar) + ain * poly2(cug, usg));
+                            f[3][q] = wq * ((ar - ain) + (C(1) - ain) * poly2(cul, usl));
                         } else {
-                            const C wq = C(L::w[q]);
                             C usg = C(0), usl = C(0);
 #pragma unroll
                             for (int a = 0; a < D; ++a) {
@@ -315,78 +480,94 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
                                 usl += ulB[a] * ulB[a];
                             }
                             const C cug = dotc<L>(q, ugB), cul = dotc<L>(q, ulB);
+                            const C eg = C(4.5) * cug * cug - C(1.5) * usg, el = C(4.5) * cul * cul - C(1.5) * usl;
                             // ABB(I), Eq. (164), eps = phi = 1
-                            f[0][q] = -fo[0] + wq * (C(9) * cug * cug - C(3) * usg);
-                            f[1][q] = -fo[1] + wq * (C(9) * cul * cul - C(3) * usl);
+                            f[0][q] = -fo[0] + C(2) * wq * eg;
+                            f[1][q] = -fo[1] + C(2) * wq * el;
                             // ABB(S)
-                            f[2][q] = -fo[2] + C(2) * wq * agB * (C(1) + C(4.5) * cug * cug - C(1.5) * usg);
-                            f[3][q] = -fo[3] + C(2) * wq * (dalB + (C(1) + dalB) * (C(4.5) * cul * cul - C(1.5) * usl));
+                            f[2][q] = -fo[2] + C(2) * wq * ((agB - ar) + agB * eg);
+                            f[3][q] = -fo[3] + C(2) * wq * ((alB - (C(1) - ar)) + alB * el);
                         }
                     }
                 }
             }
         }
 
-        // ----------------------------- continuity sources from f_b (Eq. (107))
-        C Sg = C(0), Sl = C(0);
+        // ---------- continuity sources from f_b (Eq. (107)) and own record
+        C Sg = C(0), Sl = C(0), lam_prev = C(0);
+        if (!general) {
+            // descriptor base moved back by the largest pull shift so that
+            // every per-direction SGPR offset is non-negative
+            const long long ms = (long long)p.nx + 1 + (D == 3 ? nxy : 0);
+            const __amdgpu_buffer_rsrc_t rc = rsrc(cfin - ms);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const C wq = C(L::w[q]);
-            bool wall = false, flow = false;
-            if constexpr (CH) {
-                if (edge) {
+            for (int q = 0; q < Q; ++q) {
+                const long long dq = -((long long)L::c[q][0] + (long long)L::c[q][1] * p.nx + L::c[q][2] * nxy);
+                const Rec4<C> r = ld_rec(rc, rb, (unsigned)((dq + ms) * (long long)sizeof(Rec4<C>)), C(0));
+                C du[D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) du[a] = r.v[1 + a];
+                if (q == 0 && D == 2) lam_prev = r.v[3];
+                const C als = p.renorm ? C(1) - r.v[0] : *at(alin + dq, cb);
+                C dbg, dbl;
+                beta_dev<L>(q, r.v[0], als, du, dbg, dbl);
+                Sg -= dbg;
+                Sl -= dbl;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const C wq = C(L::w[q]);
+                bool wall = false, flow = false;
+                if constexpr (CH) {
+                    if (edge) {
+#pragma unroll
+                        for (int a = 0; a < D; ++a) {
+                            wall = wall || (lo[a] && L::c[q][a] == 1 && p.wall_lo[a]) ||
+                                   (hi[a] && L::c[q][a] == -1 && p.wall_hi[a]);
+                        }
+                        if (!wall && fs >= 0) {
+                            const int cfa = fa == 0 ? L::c[q][0] : (fa == 1 ? L::c[q][1] : L::c[q][2]);
+                            flow = (fs == 0 && cfa == 1) || (fs == 1 && cfa == -1);
+                        }
+                    }
+                }
+                if (wall) continue;  // EQ(S)(1, 0) = w_q: zero deviation
+                C dbg, dbl;
+                if (flow) {
+                    C usg = C(0), usl = C(0);
 #pragma unroll
                     for (int a = 0; a < D; ++a) {
-                        wall = wall || (lo[a] && L::c[q][a] == 1 && p.wall_lo[a]) ||
-                               (hi[a] && L::c[q][a] == -1 && p.wall_hi[a]);
+                        usg += cgB[a] * cgB[a];
+                        usl += clB[a] * clB[a];
                     }
-                    if (!wall && fs >= 0) {
-                        const int cfa = fa == 0 ? L::c[q][0] : (fa == 1 ? L::c[q][1] : L::c[q][2]);
-                        flow = (fs == 0 && cfa == 1) || (fs == 1 && cfa == -1);
-                    }
-                }
-            }
-            if (wall) continue;  // EQ(S)(1, 0) = w_q: zero deviation
-            C dbg, dbl;
-            if (flow) {
-                C usg = C(0), usl = C(0);
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    usg += cgB[a] * cgB[a];
-                    usl += clB[a] * clB[a];
-                }
-                dbg = wq * (dbgB + (C(1) + dbgB) * poly2(dotc<L>(q, cgB), usg));
-                dbl = wq * (dblB + (C(1) + dblB) * poly2(dotc<L>(q, clB), usl));
-            } else {
-                const int xs = wrap_axis(x - L::c[q][0], p.nx, p.per[0]);
-                const int ys = wrap_axis(y - L::c[q][1], p.ny, p.per[1]);
-                const int zs = wrap_axis(z - L::c[q][2], p.nz, p.per[2]);
-                const long long src = ((long long)zs * p.ny + ys) * p.nx + xs;
-                C as, als, du[D];
-                if constexpr (INIT) {
-                    as = C(b.stage[src]);
-                    als = C(1) - as;
-#pragma unroll
-                    for (int a = 0; a < D; ++a) du[a] = C(b.stage[(1 + a) * n + src] - b.stage[(1 + D + a) * n + src]);
+                    dbg = wq * (dbgB + (C(1) + dbgB) * poly2(dotc<L>(q, cgB), usg));
+                    dbl = wq * (dblB + (C(1) + dblB) * poly2(dotc<L>(q, clB), usl));
                 } else {
-                    as = cfin[src];
+                    const int xs = wrap_axis(x - L::c[q][0], p.nx, p.per[0]);
+                    const int ys = wrap_axis(y - L::c[q][1], p.ny, p.per[1]);
+                    const int zs = wrap_axis(z - L::c[q][2], p.nz, p.per[2]);
+                    const long long src = ((long long)zs * p.ny + ys) * p.nx + xs;
+                    C as, als, du[D];
+                    if constexpr (INIT) {
+                        as = C(b.stage[src]);
+                        als = C(1) - as;
 #pragma unroll
-                    for (int a = 0; a < D; ++a) du[a] = cfin[(1 + a) * n + src];
-                    als = p.renorm ? C(1) - as : cfin[(1 + D) * n + src];
-                }
-                C cg[D], cl[D], usg = C(0), usl = C(0);
+                        for (int a = 0; a < D; ++a)
+                            du[a] = C(b.stage[(1 + a) * n + src] - b.stage[(1 + D + a) * n + src]);
+                    } else {
+                        const Rec4<C> r = *at(cfin, (unsigned)src * (unsigned)sizeof(Rec4<C>));
+                        as = r.v[0];
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    cg[a] = als * du[a];
-                    cl[a] = as * (-du[a]);
-                    usg += cg[a] * cg[a];
-                    usl += cl[a] * cl[a];
+                        for (int a = 0; a < D; ++a) du[a] = r.v[1 + a];
+                        if (q == 0 && D == 2) lam_prev = r.v[3];
+                        als = p.renorm ? C(1) - as : *at(alin, (unsigned)src * (unsigned)sizeof(C));
+                    }
+                    beta_dev<L>(q, as, als, du, dbg, dbl);
                 }
-                dbg = wq * poly2(dotc<L>(q, cg), usg);
-                dbl = wq * poly2(dotc<L>(q, cl), usl);
+                Sg -= dbg;
+                Sl -= dbl;
             }
-            Sg -= dbg;
-            Sl -= dbl;
         }
 
         if (ctl.write_diag) {
@@ -400,7 +581,7 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
         }
 
         // ------------------------------------------------------- moments
-        C deg = C(0), del = C(0), ag = C(0), dal = C(0);
+        C deg = C(0), del = C(0), sag = C(0), sal = C(0);
         C ug[D], ul[D], Jg[D], Jl[D], Pg[NPI], Pl[NPI];
 #pragma unroll
         for (int a = 0; a < D; ++a) ug[a] = ul[a] = Jg[a] = Jl[a] = C(0);
@@ -410,8 +591,8 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
         for (int q = 0; q < Q; ++q) {
             deg += f[0][q];  // Eq. (40), deviation from 1
             del += f[1][q];
-            ag += f[2][q];   // Eq. (73)
-            dal += f[3][q];
+            sag += f[2][q];  // Eq. (73), deviation from alpha_r
+            sal += f[3][q];  // deviation from 1 - alpha_r
 #pragma unroll
             for (int a = 0; a < D; ++a) {
                 const int ca = L::c[q][a];
@@ -424,36 +605,40 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
 #pragma unroll
                 for (int bb = a; bb < D; ++bb) {
                     const int cab = ca * L::c[q][bb];
-                    if (cab != 0) {  // second moment minus c_s^2 I
+                    if (cab != 0) {  // second moment minus c_s^2 I (sum_q w_q v v = c_s^2 I)
                         Pg[sym<D>(a, bb)] += cab * f[0][q];
                         Pl[sym<D>(a, bb)] += cab * f[1][q];
                     }
                 }
             }
         }
-        // Pi - c_s^2 I from deviations: sum_q w_q v v = c_s^2 I
-        const C al_raw = C(1) + dal;
+        const C ag = ar + sag;               // raw zeroth moments
+        const C al_raw = (C(1) - ar) + sal;
 
         // ------------------------------- Spalding renormalisation, Eq. (93)
-        C alg, all, dall;
+        C alg, all, dag;  // dag = alpha_g - alpha_r
         if (p.renorm) {
             if (ag >= C(0) && ag <= C(1) && al_raw >= C(0) && al_raw <= C(1)) {
                 // B is the identity: alpha_g = a_g / (a_g + a_l), written around
                 // a_g + a_l = 1 so that FP32 keeps the small correction exactly
-                const C e = ag + dal;  // a_g + a_l - 1
-                alg = ag - ag * e / (C(1) + e);
+                const C e = sag + sal;  // a_g + a_l - 1
+                const C corr = ag * e / (C(1) + e);
+                alg = ag - corr;
+                dag = sag - corr;
             } else {
                 const C Bg = clamp01(ag), Bl = clamp01(al_raw);
                 const C den = Bg + Bl;
                 alg = den > C(0) ? Bg / den : C(0);
+                dag = alg - ar;
             }
             all = C(1) - alg;
-            dall = -alg;
         } else {
             alg = ag;
             all = al_raw;
-            dall = dal;
+            dag = sag;
         }
+        // alpha_l - (1 - alpha_r)
+        const C dal = p.renorm ? -dag : sal;
 
         // ---------------------- sources, dashpots (Eqs. (128), (131)), lag
         C usg = C(0), usl = C(0);
@@ -469,15 +654,19 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
         const C Lam = alg * all * (alg + all * R);  // Eq. (136)
         C S2g = Spg, S2l = Spl, Laml = Lam;
         if (p.use_lag) {
-            C* lag = static_cast<C*>(b.lag);
+            Rec2<C>* lag = static_cast<Rec2<C>*>(b.lag);
+            C* lagl = static_cast<C*>(b.lag_lam);
             if (ctl.refresh) {
-                lag[node] = Spg;
-                lag[n + node] = Spl;
-                lag[2 * n + node] = Lam;
+                Rec2<C> r;
+                r.v[0] = Spg;
+                r.v[1] = Spl;
+                *at(lag, (unsigned)node * (unsigned)sizeof(Rec2<C>)) = r;
+                if (D == 3) *at(lagl, cb) = Lam;
             } else {
-                S2g = lag[node];
-                S2l = lag[n + node];
-                Laml = lag[2 * n + node];
+                const Rec2<C> r = *at(lag, (unsigned)node * (unsigned)sizeof(Rec2<C>));
+                S2g = r.v[0];
+                S2l = r.v[1];
+                Laml = D == 3 ? *at(lagl, cb) : lam_prev;
             }
         }
 
@@ -543,6 +732,11 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
 
         // ---------------------------------------------------- collisions
         T* pout = static_cast<T*>(b.pop_out);
+        // the node's own block: plane descriptor, wave-uniform block offset,
+        // per-lane lane offset
+        const __amdgpu_buffer_rsrc_t ro = rsrc(pout + (long long)z * p.plane);
+        const long long oblk = ((long long)y * p.nxb + (x >> 6)) * kBlk;
+        const unsigned vl = (unsigned)((x & 63) * (int)sizeof(T));
         {
             const C w0 = C(L::w[0]);
             const C k0 = (C(1) - w0) / w0;
@@ -560,26 +754,28 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
                 const C feql = wq * ((q == 0 ? el0 : dphiel) + pl);           // Eq. (37), phi of Eq. (32)
                 const C fLg = wq * (S2g * (q == 0 ? eg0 : C(p.psi_g)) + C(3) * cGg);  // Eq. (42)
                 const C fLl = wq * (S2l * (q == 0 ? el0p : C(p.psi_l)) + C(3) * cGl);
-                const C feqa = wq * alg * (C(1) + pg);                        // Eq. (72)
-                const C feqb = wq * (dall + all * pl);
+                const C feqa = wq * (dag + alg * pg);                         // Eq. (72)
+                const C feqb = wq * (dal + all * pl);
                 const C o0 = f[0][q] + og * (feqg - f[0][q]) + fLg;
                 const C o1 = f[1][q] + ol * (feql - f[1][q]) + fLl;
                 const C o2 = f[2][q] + oag * (feqa - f[2][q]);
                 const C o3 = f[3][q] + oal * (feqb - f[3][q]);
-                S::st(pout + (long long)(0 * Q + q) * n + node, o0);
-                S::st(pout + (long long)(1 * Q + q) * n + node, o1);
-                S::st(pout + (long long)(2 * Q + q) * n + node, o2);
-                S::st(pout + (long long)(3 * Q + q) * n + node, o3);
+                Buf<T>::st(ro, vl, (unsigned)((oblk + (0 * Q + q) * 64) * (long long)sizeof(T)), o0);
+                Buf<T>::st(ro, vl, (unsigned)((oblk + (1 * Q + q) * 64) * (long long)sizeof(T)), o1);
+                Buf<T>::st(ro, vl, (unsigned)((oblk + (2 * Q + q) * 64) * (long long)sizeof(T)), o2);
+                Buf<T>::st(ro, vl, (unsigned)((oblk + (3 * Q + q) * 64) * (long long)sizeof(T)), o3);
             }
         }
 
-        // ------------- imposed-velocity fields of the source schemes (Eq. (97))
+        // ------------ imposed-velocity record of the source schemes (Eq. (97))
         {
-            C* cf = static_cast<C*>(b.cf_out);
-            cf[node] = alg;
+            Rec4<C> r;
+            r.v[0] = alg;
 #pragma unroll
-            for (int a = 0; a < D; ++a) cf[(1 + a) * n + node] = ug[a] - ul[a];
-            if (!p.renorm) cf[(1 + D) * n + node] = all;
+            for (int a = 0; a < D; ++a) r.v[1 + a] = ug[a] - ul[a];
+            if (D == 2) r.v[3] = Laml;  // carried forward for the lagged drag
+            st_rec(rsrc(b.cf_out), rb, r);
+            if (!p.renorm) *at(static_cast<C*>(b.al_out), cb) = all;
         }
 
         // -------------------- side buffers for the next step's face values
@@ -630,8 +826,8 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
             m[(2 + 2 * D) * n + node] = double(deg) / 3.0;
         }
         if (ctl.write_diag) {
-            dsum[0] = double(ag);
-            dsum[1] = double(al_raw);
+            dsum[0] = double(ar) + double(sag);
+            dsum[1] = (1.0 - double(ar)) + double(sal);
             dsum[2] = double(alg);
             dsum[3] = double(all);
             dsum[4] = double(deg);
@@ -642,7 +838,7 @@ __global__ void __launch_bounds__(256) EELBM_WPE k_step(const KParams p, const K
                 dsum[9 + a] = double(ul[a]);
                 dsum[12 + a] = p.rho_g * double(alg) * double(ug[a]) + p.rho_l * double(all) * double(ul[a]);
             }
-            dsum[15] = double(alg) - double(ag);
+            dsum[15] = double(dag) - double(sag);
         }
     }
 

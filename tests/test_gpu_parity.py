@@ -160,7 +160,7 @@ def test_launch_shape_does_not_change_results():
     is computed by one thread from the same inputs in the same order)."""
     cfg, f = workloads.channel_2d(nx=200, ny=72, n_ramp=30.0)
     ref = None
-    for shape in [(256, 1, 1), (64, 1, 0), (64, 4, 1), (32, 8, 1), (128, 2, 0), (64, 2, 1)]:
+    for shape in [(256, 1, 1), (64, 1, 0), (64, 4, 1), (192, 1, 1), (128, 2, 0), (64, 2, 1)]:
         g = run_gpu(cfg, f, 0, "fp32")
         g.set_launch(*shape)
         assert g.get_launch() == shape
@@ -175,7 +175,7 @@ def test_launch_shape_does_not_change_results():
         assert abs(d["alpha_g"] - dref["alpha_g"]) < 1e-9
     from paper_2409_10399_amd import EelbmError
     with pytest.raises(EelbmError):
-        g.set_launch(48, 1)
+        g.set_launch(32, 8)
 
 
 def test_advance_zero_and_errors():
