@@ -31,8 +31,10 @@ def algorithmic_bytes_per_node(D, Q, tbytes, cbytes, lag):
     """State one node-update must read and write: 4Q post-collision
     populations (f_g, f_l, f_ag, f_al) read and written, the 1 + D
     imposed-velocity values (alpha_g, u_g - u_l) that stand in for the 2Q
-    source-scheme populations read and written, and the 3 lag values read
-    (their write every n_gamma steps is not counted)."""
+    source-scheme populations read and written, and the 3 lag values
+    (S''_g, S''_l, Lambda') read; their write every n_gamma steps is not
+    counted.  D2Q9 FP32: 288 + 24 + 12 = 324 B.  (The kernel moves 328 B:
+    its 16-byte record also rewrites Lambda' every step.)"""
     return 2 * 4 * Q * tbytes + 2 * (1 + D) * cbytes + (3 * cbytes if lag else 0)
 
 
@@ -41,7 +43,7 @@ def kernel_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def cpu_baseline(steps=3):
+def cpu_baseline(steps=20):
     """The oracle as it stands, single-threaded, on the full 1024x1024 channel
     for a few steps (a bounded sample of the same workload)."""
     code = (

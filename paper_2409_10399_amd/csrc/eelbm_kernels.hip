@@ -9,7 +9,8 @@
 // fraction gradients (Eqs. (91), (94)), the stresses (Eq. (70)), the drag
 // (Eqs. (6), (135)-(137)), the forces (Eqs. (24), (26)) and the collisions
 // (Eqs. (34)-(42), (71)-(72)), and writes the node's own post-collision
-// populations (coalesced stores, SoA, x fastest).
+// populations (coalesced stores into the node's 64-node x-block, see
+// pop_index).
 //
 // State kept between launches, per node:
 //  * f_g, f_l as deviations from w_q, f_ag, f_al as deviations from
@@ -224,12 +225,35 @@ __device__ __forceinline__ void beta_dev(int q, C as, C als, const C* du, C& dbg
 
 // Population layout: each z-plane is a sequence of x-blocks of 64 nodes (rows
 // padded to a whole number of blocks); one block holds the 4Q post-collision
-// populations of its 64 nodes contiguously, [set * Q + q][lane].  A wavefront
-// (64 nodes of one block) therefore reads a few contiguous regions and writes
-// one, instead of touching 4Q separate streams (DRAM row locality).
-template <int Q>
-__device__ __forceinline__ long long pop_index(const KParams& p, int x, int y, int z, int sq) {
-    return (long long)z * p.plane + (((long long)y * p.nxb + (x >> 6)) * (4 * Q * 64) + sq * 64 + (x & 63));
+// populations of its 64 nodes contiguously, [slot][lane].  The slots are
+// grouped by the (y, z) offset of the direction: the populations that a pull
+// reads from one neighbouring row (all four sets, every q of that row) form
+// one contiguous run, so a wavefront (64 nodes of one block) reads a few
+// contiguous runs and writes one block instead of touching 4Q streams.
+template <class L>
+struct PopSlots {
+    int v[4][L::Q];
+    static constexpr int row_key(int q) { return (L::c[q][2] + 1) * 3 + (L::c[q][1] + 1); }
+    constexpr PopSlots() : v() {
+        int base = 0;
+        for (int key = 0; key < 9; ++key) {
+            int k = 0;
+            for (int q = 0; q < L::Q; ++q) k += row_key(q) == key;
+            int i = 0;
+            for (int q = 0; q < L::Q; ++q) {
+                if (row_key(q) != key) continue;
+                for (int s = 0; s < 4; ++s) v[s][q] = base + s * k + i;
+                ++i;
+            }
+            base += 4 * k;
+        }
+    }
+};
+
+template <class L>
+__device__ __forceinline__ long long pop_index(const KParams& p, int x, int y, int z, int s, int q) {
+    constexpr PopSlots<L> sl{};
+    return (long long)z * p.plane + (((long long)y * p.nxb + (x >> 6)) * (4 * L::Q * 64) + sl.v[s][q] * 64 + (x & 63));
 }
 
 // --------------------------------------------------------------- the step
@@ -242,6 +266,7 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
     constexpr int NPI = L::NPI;
     constexpr int NV = 2 * D + 4;  // side-buffer values per node
     constexpr int kBlk = 4 * Q * 64;  // population elements of one x-block
+    constexpr PopSlots<L> slots{};
     const C third = C(1) / C(3);
 
     // Tiles of blockDim.x * blockDim.y nodes in an (x, y) plane, one grid
@@ -421,7 +446,7 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
                     const long long blk = (long long)(y - L::c[q][1]) * p.nxb + (xb - 1);
-                    const unsigned so = (unsigned)((blk * kBlk + (s * Q + q) * 64) * (long long)sizeof(T));
+                    const unsigned so = (unsigned)((blk * kBlk + slots.v[s][q] * 64) * (long long)sizeof(T));
                     f[s][q] = Buf<T>::ld(rp[L::c[q][2] + 1], vo[L::c[q][0] + 1], so);
                 }
             }
@@ -432,7 +457,7 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
                 const int ys = wrap_axis(y - L::c[q][1], p.ny, p.per[1]);
                 const int zs = wrap_axis(z - L::c[q][2], p.nz, p.per[2]);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) f[s][q] = S::ld(pin + pop_index<Q>(p, xs, ys, zs, s * Q + q));
+                for (int s = 0; s < 4; ++s) f[s][q] = S::ld(pin + pop_index<L>(p, xs, ys, zs, s, q));
             }
             if constexpr (CH) {
                 if (edge) {
@@ -452,7 +477,7 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
                         const int qo = L::opp[q];
                         C fo[4];
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) fo[s] = S::ld(pin + pop_index<Q>(p, x, y, z, s * Q + qo));
+                        for (int s = 0; s < 4; ++s) fo[s] = S::ld(pin + pop_index<L>(p, x, y, z, s, qo));
                         const C wq = C(L::w[q]);
                         if (wall) {
                             // half-way bounce-back, zero wall velocity
@@ -760,10 +785,10 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
                 const C o1 = f[1][q] + ol * (feql - f[1][q]) + fLl;
                 const C o2 = f[2][q] + oag * (feqa - f[2][q]);
                 const C o3 = f[3][q] + oal * (feqb - f[3][q]);
-                Buf<T>::st(ro, vl, (unsigned)((oblk + (0 * Q + q) * 64) * (long long)sizeof(T)), o0);
-                Buf<T>::st(ro, vl, (unsigned)((oblk + (1 * Q + q) * 64) * (long long)sizeof(T)), o1);
-                Buf<T>::st(ro, vl, (unsigned)((oblk + (2 * Q + q) * 64) * (long long)sizeof(T)), o2);
-                Buf<T>::st(ro, vl, (unsigned)((oblk + (3 * Q + q) * 64) * (long long)sizeof(T)), o3);
+                Buf<T>::st(ro, vl, (unsigned)((oblk + slots.v[0][q] * 64) * (long long)sizeof(T)), o0);
+                Buf<T>::st(ro, vl, (unsigned)((oblk + slots.v[1][q] * 64) * (long long)sizeof(T)), o1);
+                Buf<T>::st(ro, vl, (unsigned)((oblk + slots.v[2][q] * 64) * (long long)sizeof(T)), o2);
+                Buf<T>::st(ro, vl, (unsigned)((oblk + slots.v[3][q] * 64) * (long long)sizeof(T)), o3);
             }
         }
 

@@ -33,7 +33,8 @@ def run_gpu(cfg, fields, steps, storage, chunks=None):
 # The oracle holds raw FP64 populations near w_q, so its zeroth moments carry
 # an absolute rounding of ~1e-16 per step (a random walk of ~1e-14 over 1000
 # steps); an FP64 field passes if its rel-L2 or its RMS error is below the
-# bound.  FP32 storage must meet rel-L2 <= 1e-5 per field.
+# bound.  FP32 storage must meet rel-L2 <= 1e-5 per field (a per-field dict of
+# bounds states any exception, with its derivation at the test).
 FP64_REL, FP64_ABS = 1e-10, 1e-13
 
 
@@ -49,7 +50,8 @@ def check(rg, ro, storage, tol=None, label=""):
         if storage == "fp64" and tol is None:
             assert errs[k] <= FP64_REL or absr[k] <= FP64_ABS, (k, errs[k], absr[k])
         else:
-            assert errs[k] <= tol, (k, errs[k], tol)
+            t = tol[k] if isinstance(tol, dict) else tol
+            assert errs[k] <= t, (k, errs[k], t)
     return errs
 
 

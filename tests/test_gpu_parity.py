@@ -11,6 +11,13 @@ pytestmark = pytest.mark.gpu
 
 FP64_TOL = None  # rel-L2 1e-10 or RMS 1e-13, see parity.check
 FP32_TOL = 1e-5
+# The C1 box in FP32 storage: delta p_k there is ~1e-3 of the velocity part
+# of the stored deviations (|u| ~ 6e-4, |delta p_k| ~ 6e-7), so rounding the
+# stored deviations to FP32 alone -- the oracle's own FP64 step with its
+# populations rounded each step -- already gives rel-L2 1.7e-5 on delta p_k
+# after 1000 steps (test_oracle_scheme.test_fp32_storage_floor_on_box); the
+# FP32 arithmetic of the step adds a factor ~3.  Bound: 10x that floor.
+BOX_FP32_TOL = {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5, "dp_k": 1.7e-4}
 
 
 @pytest.fixture(scope="module")
@@ -19,7 +26,7 @@ def box_oracle():
     return cfg, f, run_oracle(cfg, f, 1000).read()
 
 
-@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp32", BOX_FP32_TOL)])
 def test_periodic_box_1000_steps(box_oracle, storage, tol):
     """D2Q9 64x64 periodic box, R = 10, gas fraction 0.1 + seeded modes,
     gravity on, Clift-Grace-Weber drag, 1000 steps."""
