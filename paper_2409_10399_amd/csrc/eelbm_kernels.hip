@@ -10,7 +10,7 @@
 // (Eqs. (6), (135)-(137)), the forces (Eqs. (24), (26)) and the collisions
 // (Eqs. (34)-(42), (71)-(72)), and writes the node's own post-collision
 // populations (coalesced stores into the node's 64-node x-block, see
-// pop_index).
+// pop_in_plane).
 //
 // State kept between launches, per node:
 //  * f_g, f_l as deviations from w_q, f_ag, f_al as deviations from
@@ -35,6 +35,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "eelbm.h"
 #include "eelbm_internal.hpp"
 #include "lattice.hpp"
@@ -43,43 +45,24 @@ namespace eelbm {
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------- storage
+// Compute type of a storage type: FP64 storage computes in FP64, every other
+// storage in FP32.  Populations are read exactly once per step: they are
+// loaded nontemporally so that they do not displace the imposed-velocity
+// records (read by nine nodes) and the freshly written populations, which the
+// next step reads back, from L2 and the Infinity Cache.  Stores stay ordinary
+// (measured: nontemporal stores, or nontemporal loads of the lag fields, are
+// slower on gfx950; ordinary population loads cost 15 %).
 template <class T>
-struct Store;
-// Populations are read exactly once per step: they are loaded nontemporally
-// so that they do not displace the imposed-velocity records (read by nine
-// nodes) and the freshly written populations, which the next step reads back,
-// from L2 and the Infinity Cache.  Stores stay ordinary (measured: nontemporal
-// stores, or nontemporal loads of the lag fields, are slower on gfx950).
+struct Compute {
+    using C = float;
+};
 template <>
-struct Store<double> {
+struct Compute<double> {
     using C = double;
-    static __device__ __forceinline__ double ld(const double* p) { return __builtin_nontemporal_load(p); }
-    static __device__ __forceinline__ void st(double* p, double v) { *p = v; }
-};
-template <>
-struct Store<float> {
-    using C = float;
-    static __device__ __forceinline__ float ld(const float* p) { return __builtin_nontemporal_load(p); }
-    static __device__ __forceinline__ void st(float* p, float v) { *p = v; }
-};
-template <>
-struct Store<__half> {
-    using C = float;
-    static __device__ __forceinline__ float ld(const __half* p) {
-        return __half2float(__ushort_as_half(__builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p))));
-    }
-    static __device__ __forceinline__ void st(__half* p, float v) { *p = __float2half_rn(v); }
-};
-template <>
-struct Store<__hip_bfloat16> {
-    using C = float;
-    static __device__ __forceinline__ float ld(const __hip_bfloat16* p) {
-        const unsigned short bits = __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p));
-        return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, bits));
-    }
-    static __device__ __forceinline__ void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
 };
 
 // 4-wide imposed-velocity record and 2-wide lag record (one vector load each)
@@ -126,46 +109,77 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
 }
 
+// The four sets (f_g, f_l, f_ag, f_al) of one direction of one node are
+// adjacent in memory and move with one vector access: 16 bytes in FP32, 8 in
+// FP16/BF16, 2 x 16 in FP64.
 template <class T>
-struct Buf;
+struct Pop4;
+// (Whole vectors are bit-cast and then indexed: a bit-cast of a single
+// vector element is not reliable with this compiler.)
 template <>
-struct Buf<float> {
-    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, kNT));
+struct Pop4<float> {
+    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float* o) {
+        const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, kNT));
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
     }
-    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)vo, (int)so, 0);
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const float* v) {
+        const f32x4 w = {v[0], v[1], v[2], v[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, w), r, (int)vo, (int)so, 0);
     }
 };
 template <>
-struct Buf<double> {
-    static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, kNT));
+struct Pop4<double> {
+    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double* o) {
+        const f64x2 a = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, kNT));
+        const f64x2 b =
+            __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)(so + 16), kNT));
+        o[0] = a.x;
+        o[1] = a.y;
+        o[2] = b.x;
+        o[3] = b.y;
     }
-    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double v) {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vo, (int)so, 0);
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const double* v) {
+        const f64x2 a = {v[0], v[1]}, b = {v[2], v[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, a), r, (int)vo, (int)so, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, b), r, (int)vo, (int)(so + 16), 0);
+    }
+};
+// 16-bit storage: set k sits in half-word k of the 8-byte group
+template <class H>
+struct Pop4Half {
+    static __device__ __forceinline__ float to_f(unsigned short h) {
+        if constexpr (sizeof(H) == 2 && std::is_same<H, __half>::value)
+            return __half2float(__ushort_as_half(h));
+        else
+            return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, h));
+    }
+    static __device__ __forceinline__ unsigned short from_f(float v) {
+        if constexpr (std::is_same<H, __half>::value)
+            return __half_as_ushort(__float2half_rn(v));
+        else
+            return __builtin_bit_cast(unsigned short, __float2bfloat16(v));
+    }
+    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float* o) {
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, kNT);
+        o[0] = to_f((unsigned short)(v.x & 0xffffu));
+        o[1] = to_f((unsigned short)(v.x >> 16));
+        o[2] = to_f((unsigned short)(v.y & 0xffffu));
+        o[3] = to_f((unsigned short)(v.y >> 16));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const float* v) {
+        u32x2 w;
+        w.x = (unsigned)from_f(v[0]) | ((unsigned)from_f(v[1]) << 16);
+        w.y = (unsigned)from_f(v[2]) | ((unsigned)from_f(v[3]) << 16);
+        __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)vo, (int)so, 0);
     }
 };
 template <>
-struct Buf<__half> {
-    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-        return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, kNT)));
-    }
-    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v) {
-        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, (int)vo, (int)so, 0);
-    }
-};
+struct Pop4<__half> : Pop4Half<__half> {};
 template <>
-struct Buf<__hip_bfloat16> {
-    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-        const unsigned short bits = __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, kNT);
-        return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, bits));
-    }
-    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float v) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2bfloat16(v)), r, (int)vo,
-                                              (int)so, 0);
-    }
-};
+struct Pop4<__hip_bfloat16> : Pop4Half<__hip_bfloat16> {};
 
 // wave-uniform base + 32-bit per-lane byte offset: compiles to a global
 // load/store with an SGPR base, one shared VGPR offset and an immediate
@@ -224,49 +238,26 @@ __device__ __forceinline__ void beta_dev(int q, C as, C als, const C* du, C& dbg
 }
 
 // Population layout: each z-plane is a sequence of x-blocks of 64 nodes (rows
-// padded to a whole number of blocks); one block holds the 4Q post-collision
-// populations of its 64 nodes contiguously, [slot][lane].  The slots are
-// grouped by the (y, z) offset of the direction: the populations that a pull
-// reads from one neighbouring row (all four sets, every q of that row) form
-// one contiguous run, so a wavefront (64 nodes of one block) reads a few
-// contiguous runs and writes one block instead of touching 4Q streams.
+// padded to a whole number of blocks); one block holds the post-collision
+// populations of its 64 nodes as [q][lane][set]: the four sets of a direction
+// are one 4-wide group, and a wavefront (64 nodes of one block) reads or
+// writes one contiguous run of 64 groups per direction.  Element offset of
+// the group (x, y, q) within its z-plane (a plane stays below 4 GiB, so every
+// access is a plane descriptor plus a 32-bit offset):
 template <class L>
-struct PopSlots {
-    int v[4][L::Q];
-    static constexpr int row_key(int q) { return (L::c[q][2] + 1) * 3 + (L::c[q][1] + 1); }
-    constexpr PopSlots() : v() {
-        int base = 0;
-        for (int key = 0; key < 9; ++key) {
-            int k = 0;
-            for (int q = 0; q < L::Q; ++q) k += row_key(q) == key;
-            int i = 0;
-            for (int q = 0; q < L::Q; ++q) {
-                if (row_key(q) != key) continue;
-                for (int s = 0; s < 4; ++s) v[s][q] = base + s * k + i;
-                ++i;
-            }
-            base += 4 * k;
-        }
-    }
-};
-
-template <class L>
-__device__ __forceinline__ long long pop_index(const KParams& p, int x, int y, int z, int s, int q) {
-    constexpr PopSlots<L> sl{};
-    return (long long)z * p.plane + (((long long)y * p.nxb + (x >> 6)) * (4 * L::Q * 64) + sl.v[s][q] * 64 + (x & 63));
+__device__ __forceinline__ unsigned pop_in_plane(const KParams& p, int x, int y, int q) {
+    return (unsigned)(((((long long)y * p.nxb + (x >> 6)) * L::Q + q) * 64 + (x & 63)) * 4);
 }
 
 // --------------------------------------------------------------- the step
 template <class L, class T, bool CH, bool INIT>
 __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b, const KCtl ctl) {
-    using C = typename Store<T>::C;
-    using S = Store<T>;
+    using C = typename Compute<T>::C;
     constexpr int D = L::D;
     constexpr int Q = L::Q;
     constexpr int NPI = L::NPI;
     constexpr int NV = 2 * D + 4;  // side-buffer values per node
     constexpr int kBlk = 4 * Q * 64;  // population elements of one x-block
-    constexpr PopSlots<L> slots{};
     const C third = C(1) / C(3);
 
     // Tiles of blockDim.x * blockDim.y nodes in an (x, y) plane, one grid
@@ -424,7 +415,7 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
                 f[3][q] = wq * ((ar - a0) + (C(1) - a0) * poly2(cul, us0l));
             }
         } else if (!general) {
-            // Interior wavefront (64 lanes = one x-block, see pop_index): the
+            // Interior wavefront (64 lanes = one x-block, see pop_in_plane): the
             // source of direction q lies in x-block xb of row y - c_y (plane
             // z - c_z), or in its neighbour block for the lane at the block
             // edge.  The wave-uniform part, taken from block xb - 1, goes in
@@ -435,20 +426,20 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const int src = xl - (k - 1);
-                vo[k] = (unsigned)((src < 0 ? 63 : (src > 63 ? 2 * kBlk : kBlk + src)) * (int)sizeof(T));
+                vo[k] = (unsigned)((src < 0 ? 63 * 4 : (src > 63 ? 2 * kBlk : kBlk + src * 4)) * (int)sizeof(T));
             }
             __amdgpu_buffer_rsrc_t rp[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
                 if (D == 3 || k == 1) rp[k] = rsrc(pin + (long long)(z - (k - 1)) * p.plane);
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
+            for (int q = 0; q < Q; ++q) {
+                const long long blk = (long long)(y - L::c[q][1]) * p.nxb + (xb - 1);
+                const unsigned so = (unsigned)((blk * kBlk + q * 256) * (long long)sizeof(T));
+                C g4[4];
+                Pop4<T>::ld(rp[L::c[q][2] + 1], vo[L::c[q][0] + 1], so, g4);
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    const long long blk = (long long)(y - L::c[q][1]) * p.nxb + (xb - 1);
-                    const unsigned so = (unsigned)((blk * kBlk + slots.v[s][q] * 64) * (long long)sizeof(T));
-                    f[s][q] = Buf<T>::ld(rp[L::c[q][2] + 1], vo[L::c[q][0] + 1], so);
-                }
+                for (int s = 0; s < 4; ++s) f[s][q] = g4[s];
             }
         } else {
 #pragma unroll
@@ -456,8 +447,10 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
                 const int xs = wrap_axis(x - L::c[q][0], p.nx, p.per[0]);
                 const int ys = wrap_axis(y - L::c[q][1], p.ny, p.per[1]);
                 const int zs = wrap_axis(z - L::c[q][2], p.nz, p.per[2]);
+                C g4[4];
+                Pop4<T>::ld(rsrc(pin + (long long)zs * p.plane), pop_in_plane<L>(p, xs, ys, q) * (unsigned)sizeof(T), 0, g4);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) f[s][q] = S::ld(pin + pop_index<L>(p, xs, ys, zs, s, q));
+                for (int s = 0; s < 4; ++s) f[s][q] = g4[s];
             }
             if constexpr (CH) {
                 if (edge) {
@@ -476,8 +469,8 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
                         if (!(wall || flow)) continue;
                         const int qo = L::opp[q];
                         C fo[4];
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) fo[s] = S::ld(pin + pop_index<L>(p, x, y, z, s, qo));
+                        Pop4<T>::ld(rsrc(pin + (long long)z * p.plane), pop_in_plane<L>(p, x, y, qo) * (unsigned)sizeof(T), 0,
+                                    fo);
                         const C wq = C(L::w[q]);
                         if (wall) {
                             // half-way bounce-back, zero wall velocity
@@ -761,7 +754,7 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
         // per-lane lane offset
         const __amdgpu_buffer_rsrc_t ro = rsrc(pout + (long long)z * p.plane);
         const long long oblk = ((long long)y * p.nxb + (x >> 6)) * kBlk;
-        const unsigned vl = (unsigned)((x & 63) * (int)sizeof(T));
+        const unsigned vl = (unsigned)((x & 63) * 4 * (int)sizeof(T));
         {
             const C w0 = C(L::w[0]);
             const C k0 = (C(1) - w0) / w0;
@@ -785,10 +778,8 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
                 const C o1 = f[1][q] + ol * (feql - f[1][q]) + fLl;
                 const C o2 = f[2][q] + oag * (feqa - f[2][q]);
                 const C o3 = f[3][q] + oal * (feqb - f[3][q]);
-                Buf<T>::st(ro, vl, (unsigned)((oblk + slots.v[0][q] * 64) * (long long)sizeof(T)), o0);
-                Buf<T>::st(ro, vl, (unsigned)((oblk + slots.v[1][q] * 64) * (long long)sizeof(T)), o1);
-                Buf<T>::st(ro, vl, (unsigned)((oblk + slots.v[2][q] * 64) * (long long)sizeof(T)), o2);
-                Buf<T>::st(ro, vl, (unsigned)((oblk + slots.v[3][q] * 64) * (long long)sizeof(T)), o3);
+                const C o4[4] = {o0, o1, o2, o3};
+                Pop4<T>::st(ro, vl, (unsigned)((oblk + q * 256) * (long long)sizeof(T)), o4);
             }
         }
 
