@@ -147,18 +147,25 @@ struct Pop4<double> {
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, b), r, (int)vo, (int)(so + 16), 0);
     }
 };
-// 16-bit storage: set k sits in half-word k of the 8-byte group
+// 16-bit storage: set k sits in half-word k of the 8-byte group.  FP16 holds
+// the deviations multiplied by 2^15 (exact): every deviation of magnitude in
+// [2e-9, 2) is then a normal FP16 number with relative precision 2^-11 --
+// unscaled, the liquid deviations at R = 1000 (~1e-6) would be subnormal, with
+// an absolute resolution of 6e-8.  BF16 has the exponent range of FP32 and is
+// stored unscaled.
 template <class H>
 struct Pop4Half {
+    static constexpr bool kHalf = std::is_same<H, __half>::value;
+    static constexpr float kUp = kHalf ? 32768.0f : 1.0f, kDown = kHalf ? 1.0f / 32768.0f : 1.0f;
     static __device__ __forceinline__ float to_f(unsigned short h) {
-        if constexpr (sizeof(H) == 2 && std::is_same<H, __half>::value)
-            return __half2float(__ushort_as_half(h));
+        if constexpr (kHalf)
+            return __half2float(__ushort_as_half(h)) * kDown;
         else
             return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, h));
     }
     static __device__ __forceinline__ unsigned short from_f(float v) {
-        if constexpr (std::is_same<H, __half>::value)
-            return __half_as_ushort(__float2half_rn(v));
+        if constexpr (kHalf)
+            return __half_as_ushort(__float2half_rn(v * kUp));
         else
             return __builtin_bit_cast(unsigned short, __float2bfloat16(v));
     }

@@ -71,10 +71,11 @@ def channel_2d(nx=1024, ny=1024, seed=0, alpha_in=0.05, noise=0.1, n_ramp=833.0)
     return cfg, fields
 
 
-def blob_field_3d(n, nblobs, seed=0, peak=0.3, rmin=4.0, rmax=12.0, cut=4.0):
-    """Sum of Gaussian blobs (peak 0.3, radii U[rmin, rmax]) at uniform
-    centres in a periodic n^3 box (minimum-image distances), truncated at
-    cut * r_b, clamped to [0, peak].  Returns (nz, ny, nx)."""
+def blob_field_3d(n, nblobs, seed=0, peak=0.3, rmin=4.0, rmax=12.0, cut=4.0, background=0.0):
+    """Background gas fraction plus a sum of Gaussian blobs (peak 0.3, radii
+    U[rmin, rmax]) at uniform centres in a periodic n^3 box (minimum-image
+    distances), truncated at cut * r_b, clamped to [0, peak].  Returns
+    (nz, ny, nx)."""
     rng = np.random.default_rng(seed)
     centres = rng.uniform(0.0, n, (nblobs, 3))
     radii = rng.uniform(rmin, rmax, nblobs)
@@ -91,13 +92,14 @@ def blob_field_3d(n, nblobs, seed=0, peak=0.3, rmin=4.0, rmax=12.0, cut=4.0):
         r2 = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2
         blob = np.where(r2 <= (cut * r) ** 2, peak * np.exp(-r2 / (2.0 * r * r)), 0.0)
         field[np.ix_(iz, iy, ix)] += blob
-    return np.clip(field, 0.0, peak)
+    return np.clip(background + field, 0.0, peak)
 
 
-def column_3d(n=256, nblobs=256, seed=0):
+def column_3d(n=256, nblobs=256, seed=0, background=0.01):
     """D3Q19 periodic column, up = +z, R = 1000, Clift-Grace-Weber drag for
-    3 mm bubbles, seeded Gaussian gas blobs, both phases at rest."""
-    alpha = blob_field_3d(n, nblobs, seed)
+    3 mm bubbles, seeded Gaussian gas blobs on a background gas fraction (the
+    scheme divides by alpha_g, so no node is gas-free), both phases at rest."""
+    alpha = blob_field_3d(n, nblobs, seed, background=background)
     cfg = _base("D3Q19", nx=n, ny=n, nz=n, rho_g=1.0, rho_l=1000.0, drag="cgw",
                 kappa_I=KAPPA_HAT_3MM, g_hat=G_HAT_R1000, up_axis=2, rho_ref="mixture_mean",
                 gamma=1.0, n_gamma=200)
