@@ -211,6 +211,56 @@ const char* eelbm_last_error(void);
 int eelbm_map_physical(double g, double kappa_I, double g_hat, double kappa_hat, double* c_over_tau,
                        double* c_tau, double* c);
 
+/* ----------------------------------------------------------------- batches
+ * Many independent lattices (each with its own sizes and parameters, e.g. a
+ * sweep of density ratio, bubble diameter and inlet gas fraction) advanced
+ * together: one launch per time step covers every tile of every member (a
+ * work list of (member, tile) pairs), and eelbm_batch_set_graph captures runs
+ * of steps into a HIP graph that is replayed.  Members are handles created and
+ * initialised as usual (same lattice, storage type, boundary kind and device;
+ * all at the same time step); the batch does not own them.  Results equal
+ * those of advancing every member on its own, bit for bit. */
+typedef struct eelbm_batch eelbm_batch;
+
+/* Device bytes of the batch's work area (member table, work list, clock) for
+ * the tile shape tile_x * tile_y (tile_x a multiple of 64, at most 256 nodes). */
+int eelbm_batch_bytes(eelbm_handle* const* members, int32_t n, int32_t tile_x, int32_t tile_y, size_t* bytes);
+
+/* Bind caller-owned device memory (eelbm_batch_bytes, 256-byte aligned) and
+ * the caller's stream (NULL: the null stream).  Every member takes the tile
+ * shape (its own eelbm_advance uses it too).  The batch runs on a stream of
+ * its own, ordered after the caller's stream at each eelbm_batch_advance and
+ * before the caller's later work.  Errors: EELBM_E_PARAM (mixed members, bad
+ * shape, too many tiles), EELBM_E_STATE (member not initialised, times differ). */
+int eelbm_batch_create(eelbm_handle* const* members, int32_t n, int32_t tile_x, int32_t tile_y, void* device_mem,
+                       size_t bytes, void* hip_stream, eelbm_batch** out);
+
+/* steps_per_graph = 0: one launch per step; > 0: runs of that many steps are
+ * captured once into a HIP graph and replayed (the remainder of an advance is
+ * launched directly).  Every step reads its time from a device clock, so a
+ * replay is valid at any time. */
+int eelbm_batch_set_graph(eelbm_batch* b, int32_t steps_per_graph);
+
+/* Advance every member by nsteps (asynchronous).  The last step of the
+ * advance (and of every replayed graph) writes the output fields and
+ * diagnostics of every member, so eelbm_read / eelbm_diag on a member work as
+ * after eelbm_advance.  EELBM_E_STATE if a member was advanced on its own. */
+int eelbm_batch_advance(eelbm_batch* b, int64_t nsteps);
+
+/* Release the batch (not the members or the caller's memory). */
+void eelbm_batch_destroy(eelbm_batch* b);
+
+/* ---------------------------------------------------------------- autotuner
+ * Choose the launch shape (tile_x, tile_y, xcd_remap) of a handle by timing
+ * every allowed shape for `steps` steps on the handle's own state, which is
+ * saved to host memory first and restored after every trial, so the state is
+ * unchanged.  The choice is cached per (lattice, storage, boundary kind, size
+ * class = floor(log2 nodes)) for the process; a later call for the same class
+ * applies the cached shape without timing unless force != 0.  The chosen shape
+ * is applied to the handle and returned through the non-NULL pointers. */
+int eelbm_autotune(eelbm_handle* h, int32_t steps, int32_t force, int32_t* tile_x, int32_t* tile_y,
+                   int32_t* xcd_remap);
+
 #ifdef __cplusplus
 }
 #endif

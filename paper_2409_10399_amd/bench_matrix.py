@@ -8,7 +8,8 @@ imposed-velocity record read and written, and the three lag values read when
 n_gamma > 1 (as in bench.py).
 
 python -m paper_2409_10399_amd.bench_matrix [--cases channel1024,column256] [--storages fp32,fp16,bf16]
-Prints one JSON object per case and a markdown table.
+python -m paper_2409_10399_amd.bench_matrix --sweep 512 [--sweep-steps 500]
+Prints one JSON object per case (and a markdown table).
 """
 import argparse
 import json
@@ -58,13 +59,70 @@ def time_case(cfg, fields, storage, steps, warmup):
     return e0.elapsed_time(e1) * 1e3 / steps, ok
 
 
+def batch_cases(count, steps, seed=0, tile=(64, 4), graph_steps=100):
+    """The channel sweep (count members, FP32) advanced three ways from its
+    initial state: one batched launch per step replayed from HIP graphs of
+    graph_steps steps, one batched launch per step, and every member launched
+    on its own (steps / 20 steps)."""
+    import torch
+    import workloads
+    from paper_2409_10399_amd import Batch, Lattice
+    t0 = time.time()
+    ws = workloads.channel_sweep(count=count, seed=seed)
+    nodes = sum(c["nx"] * c["ny"] for c, _ in ws)
+    lats = []
+    for cfg, f in ws:
+        lat = Lattice(cfg, storage="fp32")
+        lat.init_fields(f)
+        lat.set_launch(*tile)
+        lats.append(lat)
+    torch.cuda.synchronize()
+    print(f"# sweep: {count} channels, {nodes} nodes, set up in {time.time() - t0:.1f} s", flush=True)
+    st = torch.cuda.current_stream()
+    rows = []
+
+    def timed(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        fn(n)
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / n
+
+    for mode in ("graph", "batched", "separate"):
+        for lat, (cfg, f) in zip(lats, ws):  # every mode starts from the initial state
+            lat.init_fields(f)
+        if mode == "separate":
+            n = max(10, steps // 20)
+            us = timed(lambda k: [lat.advance(k) for lat in lats], n)
+        else:
+            b = Batch(lats, tile=tile, graph_steps=graph_steps if mode == "graph" else 0)
+            b.advance(graph_steps if mode == "graph" else 2)  # capture / warm up
+            us = timed(b.advance, steps)
+            del b
+        ok = all(lat.diag()["nonfinite"] == 0 for lat in lats)
+        bpn = bytes_per_node(2, 9, "fp32", True)
+        r = {"case": f"sweep{count}", "mode": mode, "nodes": nodes, "us_per_step": round(us, 2),
+             "MLUPS": round(nodes / us, 1), "GB_s": round(bpn * nodes / us / 1e3, 1),
+             "frac_hbm_peak": round(bpn * nodes / us / 1e3 / HBM_PEAK_GBS, 4), "finite": bool(ok)}
+        rows.append(r)
+        print(json.dumps(r), flush=True)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--cases", default="channel1024,column256")
     ap.add_argument("--storages", default="fp32,fp16,bf16")
     ap.add_argument("--steps", type=int, default=0, help="0: about 0.5 s of steps per case")
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--sweep", type=int, default=0, help="members of the batched channel sweep (0: skip)")
+    ap.add_argument("--sweep-steps", type=int, default=500)
     a = ap.parse_args()
+    if a.sweep:
+        batch_cases(a.sweep, a.sweep_steps)
+        return
     rows = []
     for case in a.cases.split(","):
         t0 = time.time()

@@ -66,6 +66,13 @@ SYMBOLS = {
     "eelbm_last_error": (ctypes.c_char_p, []),
     "eelbm_map_physical": (c_int, [c_double, c_double, c_double, c_double, POINTER(c_double),
                                    POINTER(c_double), POINTER(c_double)]),
+    "eelbm_batch_bytes": (c_int, [POINTER(c_void_p), c_int32, c_int32, c_int32, POINTER(c_size_t)]),
+    "eelbm_batch_create": (c_int, [POINTER(c_void_p), c_int32, c_int32, c_int32, c_void_p, c_size_t, c_void_p,
+                                   POINTER(c_void_p)]),
+    "eelbm_batch_set_graph": (c_int, [c_void_p, c_int32]),
+    "eelbm_batch_advance": (c_int, [c_void_p, c_int64]),
+    "eelbm_batch_destroy": (None, [c_void_p]),
+    "eelbm_autotune": (c_int, [c_void_p, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]),
 }
 
 _lib = None
@@ -211,6 +218,13 @@ class Lattice:
         _check(lib().eelbm_get_launch(self.h, byref(a), byref(b), byref(c)))
         return a.value, b.value, c.value
 
+    def autotune(self, steps=50, force=False):
+        """Time every launch shape on this lattice's own state (restored
+        afterwards), apply the fastest; cached per size class."""
+        a, b, c = c_int32(), c_int32(), c_int32()
+        _check(lib().eelbm_autotune(self.h, int(steps), int(bool(force)), byref(a), byref(b), byref(c)))
+        return a.value, b.value, c.value
+
     @property
     def t(self):
         return lib().eelbm_time(self.h)
@@ -254,3 +268,38 @@ class Lattice:
     def load(self, blob):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(lib().eelbm_load(self.h, buf, len(blob)))
+
+
+class Batch:
+    """Lattices advanced together: one launch per step over all their tiles,
+    optionally captured in HIP graphs of `graph_steps` steps."""
+
+    def __init__(self, members, tile=(64, 4), graph_steps=0, stream=None):
+        import torch
+        L = lib()
+        self.members = list(members)
+        arr = (c_void_p * len(self.members))(*[m.h for m in self.members])
+        self._arr = arr
+        n = c_size_t()
+        _check(L.eelbm_batch_bytes(arr, len(self.members), int(tile[0]), int(tile[1]), byref(n)))
+        self.mem = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        b = c_void_p()
+        _check(L.eelbm_batch_create(arr, len(self.members), int(tile[0]), int(tile[1]),
+                                    c_void_p(self.mem.data_ptr()), n, c_void_p(self.stream.cuda_stream), byref(b)))
+        self.b = b
+        if graph_steps:
+            _check(L.eelbm_batch_set_graph(self.b, int(graph_steps)))
+
+    def set_graph(self, steps):
+        _check(lib().eelbm_batch_set_graph(self.b, int(steps)))
+
+    def advance(self, nsteps):
+        _check(lib().eelbm_batch_advance(self.b, int(nsteps)))
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b is not None and _lib is not None:
+            _lib.eelbm_batch_destroy(b)
+            self.b = None
+

@@ -3,10 +3,14 @@
 // stream, read-out, diagnostics and checkpoints.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -197,10 +201,6 @@ Layout layout(const eelbm_params& p, const Geometry& g) {
     return L;
 }
 
-double ramp(double t, double ymax, double ymin, double nr) {
-    if (!(nr > 0)) return ymax;
-    return (ymax - ymin) * std::tanh(t / nr) + ymin;
-}
 
 }  // namespace
 
@@ -287,6 +287,14 @@ void fill_kparams(eelbm_handle* h) {
     k.b_l = h->b_l;
     k.gamma = p.gamma;
     k.alpha_min = p.alpha_min;
+    k.n_gamma = p.n_gamma;
+    k.a_in_max = p.alpha_in_max;
+    k.a_in_min = p.alpha_in_min;
+    k.ug_in_max = p.ug_in_max;
+    k.ug_in_min = p.ug_in_min;
+    k.ul_in_max = p.ul_in_max;
+    k.ul_in_min = p.ul_in_min;
+    k.n_ramp = p.n_ramp;
     k.alpha_ref = h->alpha_ref;
 }
 
@@ -296,10 +304,6 @@ int launch(eelbm_handle* h, bool init, int64_t t, bool last) {
     c.refresh = (t % h->p.n_gamma) == 0;
     c.write_macro = last;
     c.write_diag = last;
-    // streaming from t - 1 to t uses the inlet values at t - 1 (Eq. (153))
-    c.a_in = ramp((double)(t - 1), h->p.alpha_in_max, h->p.alpha_in_min, h->p.n_ramp);
-    c.ug_in = ramp((double)(t - 1), h->p.ug_in_max, h->p.ug_in_min, h->p.n_ramp);
-    c.ul_in = ramp((double)(t - 1), h->p.ul_in_max, h->p.ul_in_min, h->p.n_ramp);
     const int in = init ? 1 : h->cur;
     const int out = init ? 0 : 1 - h->cur;
     KBuffers b = buffers(h, in, out);
@@ -638,10 +642,11 @@ int eelbm_load(eelbm_handle* h, const void* host_buf, size_t bytes) {
     const size_t need = sizeof(s) + s.pop_bytes + s.cf_bytes + s.lag_bytes + s.side_bytes + s.macro_bytes +
                         s.part_bytes + s.noise_bytes;
     if (bytes < need) return fail(EELBM_E_SIZE, "checkpoint truncated");
-    h->cur = 0;
+    // the copy holding the state at time t is always copy t mod 2
+    h->cur = (int)(s.t & 1);
     const char* o = static_cast<const char*>(host_buf) + sizeof(s);
-    const std::pair<size_t, size_t> parts[7] = {{h->L.pop[0], s.pop_bytes}, {h->L.cf[0], s.cf_bytes},
-                                               {h->L.lag, s.lag_bytes},    {h->L.side[0], s.side_bytes},
+    const std::pair<size_t, size_t> parts[7] = {{h->L.pop[h->cur], s.pop_bytes}, {h->L.cf[h->cur], s.cf_bytes},
+                                               {h->L.lag, s.lag_bytes},    {h->L.side[h->cur], s.side_bytes},
                                                {h->L.macro, s.macro_bytes}, {h->L.partials, s.part_bytes},
                                                {h->L.noise, s.noise_bytes}};
     for (const auto& pr : parts) {
@@ -672,6 +677,306 @@ int eelbm_map_physical(double g, double kappa_I, double g_hat, double kappa_hat,
     if (c_over_tau) *c_over_tau = a;
     if (c_tau) *c_tau = b;
     if (c) *c = std::sqrt(a * b);
+    return EELBM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+struct eelbm_batch {
+    std::vector<eelbm_handle*> m;
+    int lattice, storage;
+    bool channel;
+    char* mem;
+    size_t bytes;
+    hipStream_t user;     // caller's stream: advance is ordered after its work and before later work
+    hipStream_t own;      // the batch's own stream (captures cannot use the legacy default stream)
+    hipEvent_t ev_in, ev_out;
+    size_t off_lat, off_work, off_clock;
+    long long nwork;
+    dim3 block;
+    int graph_steps;
+    hipGraphExec_t exec;
+    int exec_steps;
+};
+
+namespace {
+
+long long tiles_for(const eelbm_params& p, int bx, int by) {
+    return (long long)((p.nx + bx - 1) / bx) * ((p.ny + by - 1) / by) * p.nz;
+}
+
+int check_members(eelbm_handle* const* m, int32_t n, int32_t tx, int32_t ty) {
+    if (!m || n < 1) return fail(EELBM_E_PARAM, "a batch needs at least one lattice");
+    if (tx < 64 || ty < 1 || tx % 64 != 0 || tx * ty > 256)
+        return fail(EELBM_E_PARAM, "tile_x must be a multiple of 64, tile_x * tile_y at most 256");
+    for (int32_t i = 0; i < n; ++i) {
+        const eelbm_handle* h = m[i];
+        if (!h) return fail(EELBM_E_PARAM, "batch member is NULL");
+        if (!h->initialized) return fail(EELBM_E_STATE, "batch member not initialised");
+        if (h->p.lattice != m[0]->p.lattice || h->p.storage != m[0]->p.storage || h->g.channel != m[0]->g.channel)
+            return fail(EELBM_E_PARAM, "batch members must share lattice, storage and boundary kind");
+        if (h->device != m[0]->device) return fail(EELBM_E_PARAM, "batch members must live on one device");
+        if (h->t != m[0]->t) return fail(EELBM_E_STATE, "batch members must be at the same time step");
+        if (h->cur != (int)(h->t & 1)) return fail(EELBM_E_STATE, "internal: copy parity differs from time parity");
+        for (int32_t j = 0; j < i; ++j)
+            if (m[j] == h) return fail(EELBM_E_PARAM, "a lattice appears twice in the batch");
+    }
+    return EELBM_OK;
+}
+
+struct BatchSizes {
+    size_t lat, work, clock, total;
+    long long nwork;
+};
+BatchSizes batch_sizes(eelbm_handle* const* m, int32_t n, int32_t tx, int32_t ty) {
+    BatchSizes z{};
+    for (int32_t i = 0; i < n; ++i) z.nwork += tiles_for(m[i]->p, tx, ty);
+    z.lat = 0;
+    z.work = align256((size_t)n * sizeof(BatchLattice));
+    z.clock = z.work + align256((size_t)z.nwork * sizeof(uint2));
+    z.total = z.clock + 256;
+    return z;
+}
+
+int batch_step_launches(eelbm_batch* b, int64_t nsteps, hipStream_t s) {
+    const BatchLattice* lat = reinterpret_cast<const BatchLattice*>(b->mem + b->off_lat);
+    const uint2* work = reinterpret_cast<const uint2*>(b->mem + b->off_work);
+    long long* clock = reinterpret_cast<long long*>(b->mem + b->off_clock);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        hipError_t e = launch_batch_step(b->lattice, b->storage, b->channel, lat, work, b->nwork, clock, (int)k,
+                                         k == nsteps - 1, b->block, s);
+        if (e != hipSuccess) return hip_fail(e, "batch step launch");
+    }
+    hipError_t e = launch_clock_add(clock, nsteps, s);
+    if (e != hipSuccess) return hip_fail(e, "batch clock launch");
+    return EELBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int eelbm_batch_bytes(eelbm_handle* const* members, int32_t n, int32_t tile_x, int32_t tile_y, size_t* bytes) {
+    if (!bytes) return fail(EELBM_E_PARAM, "bytes is NULL");
+    int rc = check_members(members, n, tile_x, tile_y);
+    if (rc) return rc;
+    *bytes = batch_sizes(members, n, tile_x, tile_y).total;
+    return EELBM_OK;
+}
+
+int eelbm_batch_create(eelbm_handle* const* members, int32_t n, int32_t tile_x, int32_t tile_y, void* device_mem,
+                       size_t bytes, void* hip_stream, eelbm_batch** out) {
+    if (!out) return fail(EELBM_E_PARAM, "out is NULL");
+    *out = nullptr;
+    int rc = check_members(members, n, tile_x, tile_y);
+    if (rc) return rc;
+    const BatchSizes z = batch_sizes(members, n, tile_x, tile_y);
+    if (!device_mem) return fail(EELBM_E_PARAM, "device_mem is NULL");
+    if (reinterpret_cast<uintptr_t>(device_mem) & 255) return fail(EELBM_E_PARAM, "device buffer not 256-byte aligned");
+    if (bytes < z.total) return fail(EELBM_E_SIZE, "device buffer smaller than eelbm_batch_bytes");
+    if (z.nwork >= (1ll << 31)) return fail(EELBM_E_PARAM, "too many tiles in one batch");
+    // every member takes the batch's tile shape (its own launches use it too)
+    std::vector<BatchLattice> lat((size_t)n);
+    std::vector<uint2> work;
+    work.reserve((size_t)z.nwork);
+    for (int32_t i = 0; i < n; ++i) {
+        eelbm_handle* h = members[i];
+        set_tiles(h->p, &h->g, tile_x, tile_y, h->g.xcd_remap);
+        fill_kparams(h);
+        lat[i].p = h->kp;
+        lat[i].buf[0] = buffers(h, 0, 1);
+        lat[i].buf[1] = buffers(h, 1, 0);
+        for (int t = 0; t < h->g.nblocks; ++t) work.push_back(make_uint2((unsigned)i, (unsigned)t));
+    }
+    eelbm_batch* b = new (std::nothrow) eelbm_batch();
+    if (!b) return fail(EELBM_E_PARAM, "out of host memory");
+    b->m.assign(members, members + n);
+    b->lattice = members[0]->p.lattice;
+    b->storage = members[0]->p.storage;
+    b->channel = members[0]->g.channel;
+    b->mem = static_cast<char*>(device_mem);
+    b->bytes = bytes;
+    b->user = static_cast<hipStream_t>(hip_stream);
+    b->off_lat = z.lat;
+    b->off_work = z.work;
+    b->off_clock = z.clock;
+    b->nwork = z.nwork;
+    b->block = dim3(tile_x, tile_y, 1);
+    b->graph_steps = 0;
+    b->exec = nullptr;
+    b->exec_steps = 0;
+    const long long t0 = members[0]->t;
+    hipError_t e = hipStreamCreate(&b->own);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->mem + b->off_lat, lat.data(), lat.size() * sizeof(BatchLattice), hipMemcpyHostToDevice,
+                           b->own);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->mem + b->off_work, work.data(), work.size() * sizeof(uint2), hipMemcpyHostToDevice,
+                           b->own);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->mem + b->off_clock, &t0, sizeof(t0), hipMemcpyHostToDevice, b->own);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->own);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch setup");
+    }
+    *out = b;
+    return EELBM_OK;
+}
+
+int eelbm_batch_set_graph(eelbm_batch* b, int32_t steps_per_graph) {
+    if (!b) return fail(EELBM_E_PARAM, "batch is NULL");
+    if (steps_per_graph < 0 || steps_per_graph > 100000) return fail(EELBM_E_PARAM, "steps_per_graph out of range");
+    b->graph_steps = steps_per_graph;
+    return EELBM_OK;
+}
+
+int eelbm_batch_advance(eelbm_batch* b, int64_t nsteps) {
+    if (!b) return fail(EELBM_E_PARAM, "batch is NULL");
+    if (nsteps < 0) return fail(EELBM_E_PARAM, "nsteps < 0");
+    if (nsteps == 0) return EELBM_OK;
+    const long long t0 = b->m[0]->t;
+    for (auto* h : b->m)
+        if (h->t != t0) return fail(EELBM_E_STATE, "a batch member was advanced on its own");
+    // order after the caller's stream
+    hipError_t e = hipEventRecord(b->ev_in, b->user);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->own, b->ev_in, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch stream ordering");
+    int64_t left = nsteps;
+    const int K = b->graph_steps;
+    if (K > 0 && left >= K) {
+        if (!b->exec || b->exec_steps != K) {
+            if (b->exec) {
+                (void)hipGraphExecDestroy(b->exec);
+                b->exec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            e = hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+            int rc = batch_step_launches(b, K, b->own);
+            e = hipStreamEndCapture(b->own, &g);
+            if (rc) return rc;
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                b->exec = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            b->exec_steps = K;
+        }
+        for (; left >= K; left -= K) {
+            e = hipGraphLaunch(b->exec, b->own);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        }
+    }
+    if (left > 0) {
+        int rc = batch_step_launches(b, left, b->own);
+        if (rc) return rc;
+    }
+    e = hipEventRecord(b->ev_out, b->own);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->user, b->ev_out, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch stream ordering");
+    for (auto* h : b->m) {
+        h->t += nsteps;
+        h->cur = (int)(h->t & 1);
+        h->diag_blocks = h->g.nblocks;
+    }
+    return EELBM_OK;
+}
+
+void eelbm_batch_destroy(eelbm_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    (void)hipStreamSynchronize(b->own);
+    (void)hipEventDestroy(b->ev_in);
+    (void)hipEventDestroy(b->ev_out);
+    (void)hipStreamDestroy(b->own);
+    delete b;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+int eelbm_autotune(eelbm_handle* h, int32_t steps, int32_t force, int32_t* tile_x, int32_t* tile_y,
+                   int32_t* xcd_remap) {
+    if (!h) return fail(EELBM_E_PARAM, "handle is NULL");
+    if (!h->initialized) return fail(EELBM_E_STATE, "eelbm_init_fields not called");
+    if (steps < 1) return fail(EELBM_E_PARAM, "steps < 1");
+    // key: lattice, storage, boundary kind, size class (floor log2 of the node count)
+    int cls = 0;
+    for (long long v = h->g.n; v > 1; v >>= 1) ++cls;
+    const long long key = (((long long)h->p.lattice * 8 + h->p.storage) * 2 + (h->g.channel ? 1 : 0)) * 64 + cls;
+    static std::mutex mu;
+    static std::map<long long, std::array<int, 3>> cache;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end() && !force) {
+            set_tiles(h->p, &h->g, it->second[0], it->second[1], it->second[2]);
+            fill_kparams(h);
+            if (tile_x) *tile_x = it->second[0];
+            if (tile_y) *tile_y = it->second[1];
+            if (xcd_remap) *xcd_remap = it->second[2];
+            return EELBM_OK;
+        }
+    }
+    // trials run on the handle's own state, which is saved to host memory
+    // first and restored after every trial (bit for bit)
+    size_t need = 0;
+    int rc = eelbm_save(h, nullptr, &need);
+    if (rc) return rc;
+    std::vector<char> snap(need);
+    rc = eelbm_save(h, snap.data(), &need);
+    if (rc) return rc;
+    const int bx_max = std::min(256, ((h->p.nx + 63) / 64) * 64);
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    float best = 1e30f;
+    std::array<int, 3> pick = {(int)h->g.block.x, (int)h->g.block.y, h->g.xcd_remap};
+    for (int bx = 64; bx <= bx_max; bx += 64) {
+        for (int by = 1; bx * by <= 256; by *= 2) {
+            if (by > h->p.ny) break;
+            for (int xcd = 0; xcd < 2; ++xcd) {
+                set_tiles(h->p, &h->g, bx, by, xcd);
+                fill_kparams(h);
+                rc = eelbm_advance(h, 2);
+                if (!rc) e = hipEventRecord(e0, h->stream);
+                if (!rc && e == hipSuccess) rc = eelbm_advance(h, steps);
+                if (!rc && e == hipSuccess) e = hipEventRecord(e1, h->stream);
+                if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                const int rc2 = eelbm_load(h, snap.data(), snap.size());
+                if (rc || rc2 || e != hipSuccess) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+                    return rc ? rc : rc2;
+                }
+                if (ms < best) {
+                    best = ms;
+                    pick = {bx, by, xcd};
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_tiles(h->p, &h->g, pick[0], pick[1], pick[2]);
+    fill_kparams(h);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        cache[key] = pick;
+    }
+    if (tile_x) *tile_x = pick[0];
+    if (tile_y) *tile_y = pick[1];
+    if (xcd_remap) *xcd_remap = pick[2];
     return EELBM_OK;
 }
 

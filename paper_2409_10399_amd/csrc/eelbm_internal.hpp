@@ -34,6 +34,8 @@ struct KParams {
     double b_g, b_l;    // buoyancy accelerations along up
     double gamma, alpha_min;
     double alpha_ref;   // reference of the f_alpha deviations (mean initial alpha_g)
+    long long n_gamma;  // lag refresh period
+    double a_in_max, a_in_min, ug_in_max, ug_in_min, ul_in_max, ul_in_min, n_ramp;  // inlet ramp, Eq. (153)
 };
 
 // Device pointers of one launch (ping-pong halves already selected).
@@ -57,15 +59,26 @@ struct KBuffers {
 // Per-launch control.
 struct KCtl {
     long long t;          // time of the collision performed by this launch
-    int refresh;          // t mod n_gamma == 0
+    int refresh;          // lag refresh: t mod n_gamma == 0 (Eqs. (133), (137))
     int write_macro;
     int write_diag;
-    double a_in, ug_in, ul_in;  // inlet ramp values at t - 1 (streaming t-1 -> t)
+};
+
+// One lattice of a batch: its parameters and its buffers for both parities
+// (buf[0]: read copy 0 / write copy 1, the step from even to odd time).
+struct BatchLattice {
+    KParams p;
+    KBuffers buf[2];
 };
 
 // storage: 0 FP64, 1 FP32, 2 FP16, 3 BF16; lattice: 2 D2Q9, 3 D3Q19
 hipError_t launch_step(int lattice, int storage, bool channel, bool init, const KParams& p,
                        const KBuffers& b, const KCtl& c, dim3 grid, dim3 block, hipStream_t s);
+// one step of every lattice of a batch: grid = work items (lattice, tile)
+hipError_t launch_batch_step(int lattice, int storage, bool channel, const BatchLattice* lat, const uint2* work,
+                             long long nwork, const long long* clock, int k, int write_last, dim3 block,
+                             hipStream_t s);
+hipError_t launch_clock_add(long long* clock, long long add, hipStream_t s);
 hipError_t launch_sum(const double* x, long long n, double* partials, int nblocks, double* out,
                       hipStream_t s);
 hipError_t launch_diag_finalize(const double* partials, int nblocks, double* out, hipStream_t s);

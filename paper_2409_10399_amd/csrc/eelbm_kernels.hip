@@ -257,8 +257,17 @@ __device__ __forceinline__ unsigned pop_in_plane(const KParams& p, int x, int y,
 }
 
 // --------------------------------------------------------------- the step
+// inlet ramp of Eq. (153): (y_max - y_min) tanh(t / n_t) + y_min
+__device__ __forceinline__ double ramp(double t, double ymax, double ymin, double nr) {
+    if (!(nr > 0.0)) return ymax;
+    return (ymax - ymin) * tanh(t / nr) + ymin;
+}
+
+// One node update of one tile: `tile` is the tile's index over all planes,
+// `part` the slot of its diagnostic partial sums.
 template <class L, class T, bool CH, bool INIT>
-__global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b, const KCtl ctl) {
+__device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, const KCtl& ctl, long long tile,
+                                          long long part) {
     using C = typename Compute<T>::C;
     constexpr int D = L::D;
     constexpr int Q = L::Q;
@@ -266,17 +275,6 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
     constexpr int NV = 2 * D + 4;  // side-buffer values per node
     constexpr int kBlk = 4 * Q * 64;  // population elements of one x-block
     const C third = C(1) / C(3);
-
-    // Tiles of blockDim.x * blockDim.y nodes in an (x, y) plane, one grid
-    // dimension over all tiles of all planes.  Workgroups are dispatched to
-    // the 8 XCDs round-robin; with the XCD remap, XCD k receives one
-    // contiguous run of tiles, so the rows a pull reads from neighbouring
-    // tiles are mostly already in that XCD's L2.
-    long long tile = blockIdx.x;
-    if (p.xcd_remap) {
-        const long long nb = gridDim.x, per = nb >> 3;
-        if (tile < per * 8) tile = (tile & 7) * per + (tile >> 3);
-    }
     const long long plane_tiles = (long long)p.ntx * p.nty;
     const int z = (int)(tile / plane_tiles);
     const int rem = (int)(tile - (long long)z * plane_tiles);
@@ -286,7 +284,6 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
     const bool act = x < p.nx && y < p.ny;
     const long long n = p.n;
     const long long node = ((long long)z * p.ny + y) * p.nx + x;
-    const unsigned tb = (unsigned)node * (unsigned)sizeof(T);         // byte offset in a population array
     const unsigned rb = (unsigned)node * (unsigned)sizeof(Rec4<C>);   // ... in the record array
     const unsigned cb = (unsigned)node * (unsigned)sizeof(C);         // ... in a scalar array
     const int co[3] = {x, y, z};
@@ -347,12 +344,17 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
             if (fs >= 0) {
                 const C sgn = fs == 0 ? C(1) : C(-1);
                 if (ftype == EELBM_BC_INLET) {
+                    // inlet ramp at t - 1 (streaming t - 1 -> t), Eq. (153)
+                    const double tr = double(ctl.t - 1);
+                    const double a_in_t = ramp(tr, p.a_in_max, p.a_in_min, p.n_ramp);
+                    const double ug_in_t = ramp(tr, p.ug_in_max, p.ug_in_min, p.n_ramp);
+                    const double ul_in_t = ramp(tr, p.ul_in_max, p.ul_in_min, p.n_ramp);
 #pragma unroll
                     for (int a = 0; a < D; ++a) {
-                        uinG[a] = a == fa ? sgn * C(ctl.ug_in) : C(0);
-                        uinL[a] = a == fa ? sgn * C(ctl.ul_in) : C(0);
+                        uinG[a] = a == fa ? sgn * C(ug_in_t) : C(0);
+                        uinL[a] = a == fa ? sgn * C(ul_in_t) : C(0);
                     }
-                    ain = C(ctl.a_in * (b.noise ? b.noise[fidx] : 1.0));
+                    ain = C(a_in_t * (b.noise ? b.noise[fidx] : 1.0));
                 }
                 if constexpr (INIT) {
                     // t = -1: beta = 1, c from the initial fields of the edge
@@ -883,9 +885,47 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
             const int nw = (blockDim.x * blockDim.y + 63) >> 6;
             double v = 0.0;
             for (int w = 0; w < nw; ++w) v += red[tid][w];
-            b.partials[(long long)blockIdx.x * kNDiag + tid] = v;
+            b.partials[part * kNDiag + tid] = v;
         }
     }
+}
+
+// Single-lattice step: one workgroup per tile.  Workgroups are dispatched to
+// the 8 XCDs round-robin; with the XCD remap, XCD k receives one contiguous
+// run of tiles, so the rows a pull reads from neighbouring tiles are mostly
+// already in that XCD's L2.
+__device__ __forceinline__ long long xcd_tile(long long id, long long nb, int remap) {
+    if (!remap) return id;
+    const long long per = nb >> 3;
+    return id < per * 8 ? (id & 7) * per + (id >> 3) : id;
+}
+
+template <class L, class T, bool CH, bool INIT>
+__global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b, const KCtl ctl) {
+    step_body<L, T, CH, INIT>(p, b, ctl, xcd_tile(blockIdx.x, gridDim.x, p.xcd_remap), blockIdx.x);
+}
+
+// Batched step: one launch advances every lattice of a batch by one step.
+// Work item w = (lattice, tile); each lattice brings its own parameters and
+// both ping-pong buffer sets; the step's time is the batch clock + k + 1, so
+// a captured sequence of launches replays correctly at any time.
+template <class L, class T, bool CH>
+__global__ void __launch_bounds__(256) k_step_batch(const BatchLattice* lat, const uint2* work,
+                                                    const long long* clock, int k, int write_last) {
+    const uint2 w = work[xcd_tile(blockIdx.x, gridDim.x, 1)];
+    const BatchLattice& d = lat[w.x];
+    const KParams p = d.p;
+    KCtl c;
+    c.t = *clock + k + 1;
+    c.refresh = c.t % p.n_gamma == 0;
+    c.write_macro = write_last;
+    c.write_diag = write_last;
+    const KBuffers bb = d.buf[(c.t - 1) & 1];
+    step_body<L, T, CH, false>(p, bb, c, w.y, w.y);
+}
+
+__global__ void k_clock_add(long long* clock, long long add) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] += add;
 }
 
 // ---------------------------------------------------- small reductions
@@ -962,6 +1002,43 @@ hipError_t launch_step(int lattice, int storage, bool channel, bool init, const 
     if (lattice == EELBM_D2Q9) return go1<D2Q9>(storage, channel, init, p, b, c, grid, block, s);
     if (lattice == EELBM_D3Q19) return go1<D3Q19>(storage, channel, init, p, b, c, grid, block, s);
     return hipErrorInvalidValue;
+}
+
+template <class L, class T>
+static hipError_t gob(bool ch, const BatchLattice* lat, const uint2* work, long long nwork, const long long* clock,
+                      int k, int write_last, dim3 block, hipStream_t s) {
+    if (ch)
+        hipLaunchKernelGGL((k_step_batch<L, T, true>), dim3((unsigned)nwork), block, 0, s, lat, work, clock, k,
+                           write_last);
+    else
+        hipLaunchKernelGGL((k_step_batch<L, T, false>), dim3((unsigned)nwork), block, 0, s, lat, work, clock, k,
+                           write_last);
+    return hipGetLastError();
+}
+
+template <class L>
+static hipError_t gob1(int storage, bool ch, const BatchLattice* lat, const uint2* work, long long nwork,
+                       const long long* clock, int k, int write_last, dim3 block, hipStream_t s) {
+    switch (storage) {
+        case EELBM_FP64: return gob<L, double>(ch, lat, work, nwork, clock, k, write_last, block, s);
+        case EELBM_FP32: return gob<L, float>(ch, lat, work, nwork, clock, k, write_last, block, s);
+        case EELBM_FP16: return gob<L, __half>(ch, lat, work, nwork, clock, k, write_last, block, s);
+        case EELBM_BF16: return gob<L, __hip_bfloat16>(ch, lat, work, nwork, clock, k, write_last, block, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_step(int lattice, int storage, bool channel, const BatchLattice* lat, const uint2* work,
+                             long long nwork, const long long* clock, int k, int write_last, dim3 block,
+                             hipStream_t s) {
+    if (lattice == EELBM_D2Q9) return gob1<D2Q9>(storage, channel, lat, work, nwork, clock, k, write_last, block, s);
+    if (lattice == EELBM_D3Q19) return gob1<D3Q19>(storage, channel, lat, work, nwork, clock, k, write_last, block, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_clock_add(long long* clock, long long add, hipStream_t s) {
+    hipLaunchKernelGGL(k_clock_add, dim3(1), dim3(64), 0, s, clock, add);
+    return hipGetLastError();
 }
 
 hipError_t launch_sum(const double* x, long long n, double* partials, int nblocks, double* out, hipStream_t s) {

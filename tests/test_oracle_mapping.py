@@ -72,3 +72,17 @@ def test_channel_workload_constants_follow_from_the_mapping():
     K = workloads.KAPPA_HAT_3MM * mapping.cgw_lambda(0.05, 1000.0)
     slip = mapping.slip_u0(K, 0.05, 1000.0, workloads.G_HAT_R1000)
     assert abs(slip / workloads.UG_IN_R1000 - 1) < 5e-3
+
+
+def test_sweep_inlet_slip_is_the_drift_flux_slip():
+    """The channel sweep's inlet gas velocity (workloads.terminal_slip) is the
+    uniform slip of Eq. (124) with the Clift-Grace-Weber coefficient
+    K_I = kappa Lambda (Eqs. (135)-(136)), from the oracle's mapping helpers."""
+    import workloads
+    from oracle import mapping
+    for R, kap, a in [(1000.0, workloads.KAPPA_HAT_3MM, 0.05), (2.0, 2.9e-4, 0.2), (37.0, 5.8e-5, 0.02)]:
+        g = 1e-6 / (R - 1.0)
+        K = kap * mapping.cgw_lambda(a, R)
+        assert abs(workloads.terminal_slip(R, kap, a, g) - mapping.slip_u0(K, a, R, g)) < 1e-15
+    assert abs(workloads.terminal_slip(1000.0, workloads.KAPPA_HAT_3MM, 0.05, workloads.G_HAT_R1000)
+               - workloads.UG_IN_R1000) < 5e-6

@@ -71,6 +71,60 @@ def channel_2d(nx=1024, ny=1024, seed=0, alpha_in=0.05, noise=0.1, n_ramp=833.0)
     return cfg, fields
 
 
+def terminal_slip(R, kappa_hat, alpha, g_hat):
+    """Closed-form uniform slip |u_g - u_l| of a drift-flux state with the
+    Clift-Grace-Weber drag: sqrt((R - 1) g_hat / (kappa_hat (alpha + (1 -
+    alpha) R))) -- the inlet gas velocity of the channel sweep (an input
+    value; a CPU test checks it against the oracle's drift-flux fixed point)."""
+    return float(np.sqrt((R - 1.0) * g_hat / (kappa_hat * (alpha + (1.0 - alpha) * R))))
+
+
+SWEEP_SLIP_CAP = 0.01
+
+
+def sweep_channel_2d(nx, ny, R, d_mm, alpha_in, seed=0, noise=0.1, n_ramp=417.0, slip_cap=None):
+    """One member of the channel sweep: the channel of channel_2d with density
+    ratio R, bubble diameter d_mm (kappa_I = 0.495 / d, mapped with the TEST #4
+    invariant c tau = 5.8586e-7 m^2/s), inlet gas fraction alpha_in and
+    (R - 1) g_hat = 1e-6, lowered where the inlet slip would exceed 0.01
+    (Mach 0.017: at R ~ 2 the invariant alone gives 0.075, and with slips
+    above ~0.015 some low-R members diverge within 5000 steps); dashpot + lag
+    (gamma = 1, n_gamma = 200) at every R (without them, most members with
+    R < 100 diverge within 5000 steps)."""
+    rng = np.random.default_rng(seed)
+    inlet_noise = 1.0 + noise * rng.uniform(-1.0, 1.0, nx)
+    kappa_hat = 0.495 / (d_mm * 1e-3) * 5.8586e-7
+    g_hat = 1e-6 / (R - 1.0)
+    ug = terminal_slip(R, kappa_hat, alpha_in, g_hat)
+    cap = SWEEP_SLIP_CAP if slip_cap is None else slip_cap
+    if ug > cap:
+        g_hat *= (cap / ug) ** 2
+        ug = terminal_slip(R, kappa_hat, alpha_in, g_hat)
+    cfg = _base("D2Q9", nx=nx, ny=ny, rho_g=1.0, rho_l=float(R), drag="cgw", kappa_I=kappa_hat, g_hat=g_hat,
+                up_axis=1, rho_ref="liquid", gamma=1.0, n_gamma=200,
+                bc={"x-": "wall", "x+": "wall", "y-": "inlet", "y+": "outlet"},
+                alpha_in_max=alpha_in, alpha_in_min=alpha_in / 10.0, ug_in_max=ug, ug_in_min=ug / 10.0,
+                ul_in_max=0.0, ul_in_min=0.0, n_ramp=n_ramp)
+    fields = dict(alpha_g=np.full((ny, nx), alpha_in / 10.0), u_g=np.zeros((2, ny, nx)),
+                  u_l=np.zeros((2, ny, nx)), dp_k=np.zeros((ny, nx)), inlet_noise=inlet_noise)
+    return cfg, fields
+
+
+def channel_sweep(count=512, seed=0, nmin=64, nmax=512, slip_cap=None):
+    """The batched sweep: `count` channels with nx, ny ~ U{nmin..nmax}
+    independently, R = exp(U[ln 2, ln 1000]), d ~ U[1, 5] mm, alpha_in ~
+    U[0.02, 0.2]; member i draws its inlet noise from seed (seed, i)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        nx, ny = (int(v) for v in rng.integers(nmin, nmax + 1, 2))
+        R = float(np.exp(rng.uniform(np.log(2.0), np.log(1000.0))))
+        d = float(rng.uniform(1.0, 5.0))
+        a = float(rng.uniform(0.02, 0.2))
+        out.append(sweep_channel_2d(nx, ny, R, d, a, seed=[seed, i], slip_cap=slip_cap))
+    return out
+
+
 def blob_field_3d(n, nblobs, seed=0, peak=0.3, rmin=4.0, rmax=12.0, cut=4.0, background=0.0):
     """Background gas fraction plus a sum of Gaussian blobs (peak 0.3, radii
     U[rmin, rmax]) at uniform centres in a periodic n^3 box (minimum-image
