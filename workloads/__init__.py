@@ -125,6 +125,41 @@ def channel_sweep(count=512, seed=0, nmin=64, nmax=512, slip_cap=None):
     return out
 
 
+def tube_1d(test=1, nx=200, n_steps=6_000_000):
+    """The paper's 1D tube tests (Sec. 3.6, TEST #1 - #4) as a D2Q9 lattice of
+    nx x 1 nodes, periodic across (the y-uniform D2Q9 run is the D1Q3 run):
+    inlet at x = 0, outlet at x = nx - 1, gravity along +x, wall friction on
+    the liquid, nu = 7/6 (omega = 0.25), omega_alpha = 1.5, psi = 0, inlet
+    ramp n_t = N_t / 12, interior initially at the ramp's minimum values.
+    TEST #1: R = 2, g_hat = 1e-6, constant K_I = K_W = 1e-2, inlet alpha_g
+    0.8 / 0.01, u_g 1e-2 / Eq. (154), u_l 1e-3 / 0.  #2: R = 5, g_hat =
+    2.5e-7.  #3: R = 833.3, g_hat = 1.2e-9, gamma = 1, n_gamma = 200.  #4:
+    as #3 with the Clift-Grace-Weber drag kappa = kappa_W = 1.45e-4, inlet
+    u_g 0.0043 / 0.00043, u_l 0.0011 / 0.00011, alpha_g 0.1 / 0.01."""
+    R, g = {1: (2.0, 1e-6), 2: (5.0, 2.5e-7), 3: (1000.0 / 1.2, 1.2e-9), 4: (1000.0 / 1.2, 1.2e-9)}[test]
+    kw = dict(nx=nx, ny=1, rho_g=1.2, rho_l=1.2 * R, up_axis=0, g_hat=g, rho_ref="liquid",
+              bc={"x-": "inlet", "x+": "outlet", "y-": "periodic", "y+": "periodic"}, n_ramp=n_steps / 12.0,
+              gamma=1.0 if test >= 3 else 0.0, n_gamma=200 if test >= 3 else 1)
+    if test < 4:
+        a_max, a_min, K = 0.8, 1e-2, 1e-2
+        ug_max, ug_min = 1e-2, float(np.sqrt(a_min * (1.0 - a_min) * (R - 1.0) * g / K))
+        ul_max, ul_min = 1e-3, 0.0
+        kw.update(drag="const", K_I=K, K_W=K)
+    else:
+        a_max, a_min, K = 0.1, 1e-2, 1.45e-4
+        ug_max, ug_min, ul_max, ul_min = 0.0043, 0.00043, 0.0011, 0.00011
+        kw.update(drag="cgw", kappa_I=K, K_W=K)
+    kw.update(alpha_in_max=a_max, alpha_in_min=a_min, ug_in_max=ug_max, ug_in_min=ug_min,
+              ul_in_max=ul_max, ul_in_min=ul_min)
+    cfg = _base("D2Q9", **kw)
+    u_g = np.zeros((2, 1, nx))
+    u_l = np.zeros((2, 1, nx))
+    u_g[0] = ug_min
+    u_l[0] = ul_min
+    fields = dict(alpha_g=np.full((1, nx), a_min), u_g=u_g, u_l=u_l, dp_k=np.zeros((1, nx)))
+    return cfg, fields
+
+
 def blob_field_3d(n, nblobs, seed=0, peak=0.3, rmin=4.0, rmax=12.0, cut=4.0, background=0.0):
     """Background gas fraction plus a sum of Gaussian blobs (peak 0.3, radii
     U[rmin, rmax]) at uniform centres in a periodic n^3 box (minimum-image
