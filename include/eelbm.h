@@ -168,6 +168,15 @@ int eelbm_create(const eelbm_params* p, void* device_mem, size_t bytes, void* hi
 int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g, const double* u_l,
                       const double* dp_k, const double* inlet_noise, int on_device);
 
+/* Rebuild the state at time t from macroscopic fields (the layout of
+ * eelbm_init_fields): populations at the local equilibria of the fields as at
+ * initialisation, the inlet ramp continuing from t, the inlet noise, the
+ * buoyancy reference and the lag fields of the run kept.  For restarting the
+ * scheme from fields predicted elsewhere (the surrogate's re-anchoring).
+ * EELBM_E_STATE before eelbm_init_fields. */
+int eelbm_reinit_fields(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u_g, const double* u_l,
+                        const double* dp_k, int on_device);
+
 /* Advance nsteps time steps (asynchronous on the bound stream).  The last
  * step also writes the output fields and the diagnostic partial sums. */
 int eelbm_advance(eelbm_handle* h, int64_t nsteps);
@@ -260,6 +269,74 @@ void eelbm_batch_destroy(eelbm_batch* b);
  * is applied to the handle and returned through the non-NULL pointers. */
 int eelbm_autotune(eelbm_handle* h, int32_t steps, int32_t force, int32_t* tile_x, int32_t* tile_y,
                    int32_t* xcd_remap);
+
+/* --------------------------------------------------- learned surrogate
+ * Kernels of a convolutional neural operator (U-Net of 3x3 convolutions)
+ * that maps the macroscopic fields of a lattice to their change over a
+ * fixed number of steps; a caller (the Python surrogate module) chains them
+ * into forward and backward passes.  Not part of the paper: the surrogate is
+ * judged against the step above.
+ *
+ * All pointers are device pointers, tensors NHWC FP32 (B images, H x W
+ * pixels, C channels, C a multiple of 16), launches are asynchronous on
+ * `stream` (a hipStream_t, NULL: the null stream).  Returns EELBM_OK,
+ * EELBM_E_PARAM for NULL pointers or unsupported shapes (the message is not
+ * set), EELBM_E_HIP if the launch failed.
+ *
+ * Convolution weights: FP32 master W[tap][ci][co] (tap = 3 (dy + 1) + dx + 1),
+ * and two BF16 copies made by eelbm_cno_pack_weights: Wf[co][tap][ci] for the
+ * forward pass and Wd[ci][tap][co] for the input gradient.  The products run
+ * on the matrix cores in BF16 with FP32 accumulation. */
+
+/* out = act(conv3x3(in; Wf) + bias), zero padding; act = leaky-ReLU with
+ * `slope` if act != 0; bias may be NULL. */
+int eelbm_cno_conv_fwd(const float* in, int32_t B, int32_t H, int32_t W, int32_t Cin, const uint16_t* wf,
+                       const float* bias, int32_t Cout, float* out, int32_t act, float slope, void* stream);
+/* din = gradient of the convolution wrt its input, given dout (the gradient
+ * wrt the pre-activation output). */
+int eelbm_cno_conv_bwd_data(const float* dout, int32_t B, int32_t H, int32_t W, int32_t Cout, const uint16_t* wd,
+                            int32_t Cin, float* din, void* stream);
+/* dw[tap][ci][co] += sum over pixels of in(shifted) * dout; dbias[co] += sum
+ * of dout (dbias may be NULL).  Accumulates: zero them first (eelbm_cno_fill).
+ * Cout <= 256. */
+int eelbm_cno_conv_bwd_weight(const float* in, const float* dout, int32_t B, int32_t H, int32_t W, int32_t Cin,
+                              int32_t Cout, float* dw, float* dbias, void* stream);
+/* dx = dy where y > 0, slope * dy elsewhere (y: the leaky-ReLU output). */
+int eelbm_cno_act_bwd(const float* y, const float* dy, int64_t n, float slope, float* dx, void* stream);
+/* 2x2 average pooling (H, W even): forward (B, H, W, C) -> (B, H/2, W/2, C);
+ * backward (backward = 1): the gradient of (B, H/2, W/2, C) spread back to
+ * (B, H, W, C) (in = that gradient, H, W the full sizes). */
+int eelbm_cno_pool(const float* in, int32_t B, int32_t H, int32_t W, int32_t C, float* out, int32_t backward,
+                   void* stream);
+/* nearest 2x upsampling: forward (B, H, W, C) -> (B, 2H, 2W, C); backward:
+ * the gradient of (B, 2H, 2W, C) summed back to (B, H, W, C). */
+int eelbm_cno_up(const float* in, int32_t B, int32_t H, int32_t W, int32_t C, float* out, int32_t backward,
+                 void* stream);
+/* out = [a | b] over channels, P pixels; split_add: da = d[:, :Ca],
+ * db += d[:, Ca:]. */
+int eelbm_cno_concat(const float* a, int32_t Ca, const float* b, int32_t Cb, int64_t P, float* out, void* stream);
+int eelbm_cno_split_add(const float* d, int32_t Ca, int32_t Cb, int64_t P, float* da, float* db, void* stream);
+/* mean squared error over the first Cused of C channels: partial[nblocks]
+ * FP64 sums (their total is the loss), dpred = its gradient (may be NULL). */
+int eelbm_cno_mse(const float* pred, const float* target, int64_t P, int32_t C, int32_t Cused, double* partial,
+                  int32_t nblocks, float* dpred, void* stream);
+/* Adam step `step` (>= 1) with decoupled weight decay on n FP32 values. */
+int eelbm_cno_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                   int64_t step, float weight_decay, void* stream);
+/* BF16 operand copies Wf and Wd of the FP32 master W (9 Cin Cout values). */
+int eelbm_cno_pack_weights(const float* w, int32_t Cin, int32_t Cout, uint16_t* wf, uint16_t* wd, void* stream);
+/* Network input: out[b][p][c] = (soa[b][c][p] - mean[c]) * inv_scale[c] for
+ * c < nf (stacked field planes, P pixels per image), cond[b][c - nf] for
+ * nf <= c < nf + nc, 0 up to C. */
+int eelbm_cno_pack(const float* soa, int64_t P, int32_t nf, const float* mean, const float* inv_scale,
+                   const float* cond, int32_t nc, int32_t B, int32_t C, float* out, void* stream);
+/* Fields after a jump: soa_out[b][f][p] = soa_in[b][f][p] + net[b][p][f] * dscale[f], f < nf. */
+int eelbm_cno_unpack(const float* soa_in, const float* net, int64_t P, int32_t nf, int32_t C, const float* dscale,
+                     int32_t B, float* soa_out, void* stream);
+/* y += a x over n values. */
+int eelbm_cno_axpy(const float* x, int64_t n, float a, float* y, void* stream);
+/* p[0..n) = value (a kernel, usable inside captured graphs). */
+int eelbm_cno_fill(float* p, int64_t n, float value, void* stream);
 
 #ifdef __cplusplus
 }

@@ -73,6 +73,29 @@ SYMBOLS = {
     "eelbm_batch_advance": (c_int, [c_void_p, c_int64]),
     "eelbm_batch_destroy": (None, [c_void_p]),
     "eelbm_autotune": (c_int, [c_void_p, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]),
+    "eelbm_reinit_fields": (c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
+    # learned surrogate kernels (device pointers, NHWC FP32)
+    "eelbm_cno_conv_fwd": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int32,
+                                   c_void_p, c_int32, ctypes.c_float, c_void_p]),
+    "eelbm_cno_conv_bwd_data": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,
+                                        c_void_p]),
+    "eelbm_cno_conv_bwd_weight": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32, c_void_p,
+                                          c_void_p, c_void_p]),
+    "eelbm_cno_act_bwd": (c_int, [c_void_p, c_void_p, c_int64, ctypes.c_float, c_void_p, c_void_p]),
+    "eelbm_cno_pool": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p]),
+    "eelbm_cno_up": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p]),
+    "eelbm_cno_concat": (c_int, [c_void_p, c_int32, c_void_p, c_int32, c_int64, c_void_p, c_void_p]),
+    "eelbm_cno_split_add": (c_int, [c_void_p, c_int32, c_int32, c_int64, c_void_p, c_void_p, c_void_p]),
+    "eelbm_cno_mse": (c_int, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p]),
+    "eelbm_cno_adam": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_float, c_int64, ctypes.c_float, c_void_p]),
+    "eelbm_cno_pack_weights": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
+    "eelbm_cno_pack": (c_int, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32,
+                               c_void_p, c_void_p]),
+    "eelbm_cno_unpack": (c_int, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int32, c_void_p,
+                                 c_void_p]),
+    "eelbm_cno_axpy": (c_int, [c_void_p, c_int64, ctypes.c_float, c_void_p, c_void_p]),
+    "eelbm_cno_fill": (c_int, [c_void_p, c_int64, ctypes.c_float, c_void_p]),
 }
 
 _lib = None
@@ -206,6 +229,11 @@ class Lattice:
         ptr = lambda k: c_void_p(tensors[k].data_ptr()) if tensors.get(k) is not None else None
         _check(lib().eelbm_init_fields(self.h, ptr("alpha_g"), ptr("u_g"), ptr("u_l"), ptr("dp_k"),
                                        ptr("inlet_noise"), 1))
+
+    def reinit_fields_device(self, t, tensors):
+        """Rebuild the state at time t from device (torch float64) fields."""
+        ptr = lambda k: c_void_p(tensors[k].data_ptr()) if tensors.get(k) is not None else None
+        _check(lib().eelbm_reinit_fields(self.h, int(t), ptr("alpha_g"), ptr("u_g"), ptr("u_l"), ptr("dp_k"), 1))
 
     def advance(self, nsteps):
         _check(lib().eelbm_advance(self.h, int(nsteps)))

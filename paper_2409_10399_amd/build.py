@@ -22,7 +22,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
-SOURCES = ["eelbm_kernels.hip", "eelbm_capi.cpp"]
+SOURCES = ["eelbm_kernels.hip", "eelbm_capi.cpp", "cno_kernels.hip"]
 
 
 def _run(cmd):

@@ -1,0 +1,594 @@
+// HIP kernels of the learned surrogate: a convolutional neural operator
+// (U-Net of 3x3 convolutions, 2x2 average pooling, nearest 2x upsampling,
+// skip concatenations, leaky-ReLU) that maps the macroscopic fields of a D2Q9
+// channel to their change over a fixed number of LBM steps.
+//
+// Tensors are NHWC, FP32 in memory; every channel count is a multiple of 16.
+// A 3x3 convolution is an implicit GEMM, M = pixels, N = output channels,
+// K = 9 * input channels ordered (tap, channel), evaluated with the 16x16x16
+// BF16 matrix-core instruction and FP32 accumulation: each wavefront owns 16
+// consecutive pixels of one image row and all output channels of its N-tile
+// group; operands are converted to BF16 as they are loaded.  Operand layout
+// of v_mfma_f32_16x16x16_bf16 (lane l, element t = 0..3):
+//   A[m = l % 16][k = 4 (l / 16) + t],  B[k = 4 (l / 16) + t][n = l % 16],
+//   D[m = 4 (l / 16) + t][n = l % 16].
+// Weights: master FP32 W[tap][ci][co]; the forward pass reads the BF16 copy
+// Wf[co][tap][ci] and the input-gradient pass the BF16 copy Wd[ci][tap][co],
+// so that the four K-consecutive values a lane needs are adjacent.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "eelbm.h"
+
+namespace cno {
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+    const unsigned u = __builtin_bit_cast(unsigned, f);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_float(unsigned short h) { return __builtin_bit_cast(float, (unsigned)h << 16); }
+
+__device__ __forceinline__ s16x4 pack4(const f32x4& v) {
+    s16x4 r;
+    r.x = (short)bf16_bits(v.x);
+    r.y = (short)bf16_bits(v.y);
+    r.z = (short)bf16_bits(v.z);
+    r.w = (short)bf16_bits(v.w);
+    return r;
+}
+
+__device__ __forceinline__ f32x4 mfma(const s16x4& a, const s16x4& b, const f32x4& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+constexpr int kMaxNT = 12;  // output-channel tiles of 16 one wavefront accumulates (192 channels)
+
+// --------------------------------------------------------------- forward
+// out[b, y, x, co] = bias[co] + sum_{tap, ci} in[b, y + dy, x + dx, ci] Wf[co][tap][ci]
+// (zero padding), then leaky-ReLU with slope `slope` if act != 0.
+// Grid: x = pixel groups of 16 (rows padded), y = groups of NT output tiles.
+template <int NT>
+__global__ void __launch_bounds__(64) k_conv_fwd(const float* __restrict__ in, int B, int H, int W, int Cin,
+                                                const unsigned short* __restrict__ wf, const float* __restrict__ bias,
+                                                int Cout, float* __restrict__ out, int act, float slope) {
+    const int lane = threadIdx.x;
+    const int gw = (W + 15) / 16;
+    const long long grp = blockIdx.x;
+    const int xg = (int)(grp % gw);
+    const long long by = grp / gw;  // b * H + y
+    const int y = (int)(by % H);
+    const int b = (int)(by / H);
+    const int x = xg * 16 + (lane & 15);  // pixel of this lane's A row
+    const int kq = 4 * (lane >> 4);       // K offset of this lane within a 16-chunk
+    const int n0 = blockIdx.y * NT * 16;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int K = 9 * Cin;
+    for (int tap = 0; tap < 9; ++tap) {
+        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+        const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const float* src = in + (((long long)b * H + (ok ? yy : 0)) * W + (ok ? xx : 0)) * Cin;
+        for (int c0 = 0; c0 < Cin; c0 += 16) {
+            f32x4 av = ok ? *reinterpret_cast<const f32x4*>(src + c0 + kq) : f32x4{0.f, 0.f, 0.f, 0.f};
+            const s16x4 a = pack4(av);
+            const int k = tap * Cin + c0 + kq;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int co = n0 + j * 16 + (lane & 15);
+                const u16x4 wv = co < Cout ? *reinterpret_cast<const u16x4*>(wf + (long long)co * K + k)
+                                           : u16x4{0, 0, 0, 0};
+                acc[j] = mfma(a, __builtin_bit_cast(s16x4, wv), acc[j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int co = n0 + j * 16 + (lane & 15);
+        if (co >= Cout) continue;
+        const float bc = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int px = xg * 16 + 4 * (lane >> 4) + t;
+            if (px >= W) continue;
+            float v = acc[j][t] + bc;
+            if (act) v = v > 0.f ? v : slope * v;
+            out[(((long long)b * H + y) * W + px) * Cout + co] = v;
+        }
+    }
+}
+
+// ----------------------------------------------------- gradient wrt input
+// din[b, y, x, ci] = sum_{tap, co} dout[b, y - dy, x - dx, co] Wd[ci][tap][co]
+template <int NT>
+__global__ void __launch_bounds__(64) k_conv_bwd_data(const float* __restrict__ dout, int B, int H, int W, int Cout,
+                                                     const unsigned short* __restrict__ wd, int Cin,
+                                                     float* __restrict__ din) {
+    const int lane = threadIdx.x;
+    const int gw = (W + 15) / 16;
+    const long long grp = blockIdx.x;
+    const int xg = (int)(grp % gw);
+    const long long by = grp / gw;
+    const int y = (int)(by % H);
+    const int b = (int)(by / H);
+    const int x = xg * 16 + (lane & 15);
+    const int kq = 4 * (lane >> 4);
+    const int n0 = blockIdx.y * NT * 16;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int K = 9 * Cout;
+    for (int tap = 0; tap < 9; ++tap) {
+        const int yy = y - (tap / 3 - 1), xx = x - (tap % 3 - 1);
+        const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const float* src = dout + (((long long)b * H + (ok ? yy : 0)) * W + (ok ? xx : 0)) * Cout;
+        for (int c0 = 0; c0 < Cout; c0 += 16) {
+            f32x4 av = ok ? *reinterpret_cast<const f32x4*>(src + c0 + kq) : f32x4{0.f, 0.f, 0.f, 0.f};
+            const s16x4 a = pack4(av);
+            const int k = tap * Cout + c0 + kq;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int ci = n0 + j * 16 + (lane & 15);
+                const u16x4 wv = ci < Cin ? *reinterpret_cast<const u16x4*>(wd + (long long)ci * K + k)
+                                          : u16x4{0, 0, 0, 0};
+                acc[j] = mfma(a, __builtin_bit_cast(s16x4, wv), acc[j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int ci = n0 + j * 16 + (lane & 15);
+        if (ci >= Cin) continue;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int px = xg * 16 + 4 * (lane >> 4) + t;
+            if (px >= W) continue;
+            din[(((long long)b * H + y) * W + px) * Cin + ci] = acc[j][t];
+        }
+    }
+}
+
+// ---------------------------------------------------- gradient wrt weights
+// dW[tap][ci][co] += sum_p in[p + d_tap][ci] dout[p][co] over this
+// workgroup's chunk of `chunk` pixels (M = (tap, ci), N = co, K = pixels);
+// one wavefront per 16 x 16 tile of dW, partial sums added atomically.
+__global__ void __launch_bounds__(64) k_conv_bwd_weight(const float* __restrict__ in, const float* __restrict__ dout,
+                                                       int B, int H, int W, int Cin, int Cout, int chunk,
+                                                       float* __restrict__ dw) {
+    const int lane = threadIdx.x;
+    const int mt = blockIdx.x;  // M tile over 9 * Cin
+    const int nt = blockIdx.y;  // N tile over Cout
+    const long long P = (long long)B * H * W;
+    const long long p0 = (long long)blockIdx.z * chunk;
+    const int m = mt * 16 + (lane & 15);
+    const int tap = m / Cin, ci = m - tap * Cin;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int co = nt * 16 + (lane & 15);
+    const int kq = 4 * (lane >> 4);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (long long pk = p0; pk < p0 + chunk && pk < P; pk += 16) {
+        f32x4 av, bv;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const long long p = pk + kq + t;
+            float a = 0.f, bb = 0.f;
+            if (p < P) {
+                const int px = (int)(p % W);
+                const long long r = p / W;
+                const int py = (int)(r % H);
+                const int pb = (int)(r / H);
+                const int yy = py + dy, xx = px + dx;
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    a = in[(((long long)pb * H + yy) * W + xx) * Cin + ci];
+                bb = dout[p * Cout + co];
+            }
+            av[t] = a;
+            bv[t] = bb;
+        }
+        acc = mfma(pack4(av), pack4(bv), acc);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int mm = mt * 16 + 4 * (lane >> 4) + t;  // row of D
+        atomicAdd(dw + (long long)mm * Cout + co, acc[t]);
+    }
+}
+
+// ------------------------------------------------------------ elementwise
+__global__ void k_bias_grad(const float* __restrict__ dout, long long P, int C, float* __restrict__ db) {
+    // one workgroup per 256-pixel chunk, one thread per channel (C <= 256)
+    const int c = threadIdx.x;
+    if (c >= C) return;
+    const long long p0 = (long long)blockIdx.x * 256;
+    float s = 0.f;
+    for (long long p = p0; p < p0 + 256 && p < P; ++p) s += dout[p * C + c];
+    atomicAdd(db + c, s);
+}
+
+__global__ void k_act_bwd(const float* __restrict__ y, const float* __restrict__ dy, long long n, float slope,
+                          float* __restrict__ dx) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dx[i] = y[i] > 0.f ? dy[i] : slope * dy[i];
+}
+
+// 2x2 average pooling, (B, H, W, C) -> (B, H/2, W/2, C)
+__global__ void k_pool_fwd(const float* __restrict__ in, int B, int H, int W, int C, float* __restrict__ out) {
+    const long long n = (long long)B * (H / 2) * (W / 2) * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        long long r = i / C;
+        const int x = (int)(r % (W / 2));
+        r /= (W / 2);
+        const int y = (int)(r % (H / 2));
+        const int b = (int)(r / (H / 2));
+        const float* s = in + (((long long)b * H + 2 * y) * W + 2 * x) * C + c;
+        out[i] = 0.25f * (s[0] + s[C] + s[(long long)W * C] + s[(long long)W * C + C]);
+    }
+}
+__global__ void k_pool_bwd(const float* __restrict__ dout, int B, int H, int W, int C, float* __restrict__ din) {
+    const long long n = (long long)B * H * W * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        long long r = i / C;
+        const int x = (int)(r % W);
+        r /= W;
+        const int y = (int)(r % H);
+        const int b = (int)(r / H);
+        din[i] = 0.25f * dout[(((long long)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
+    }
+}
+// nearest 2x upsampling, (B, H, W, C) -> (B, 2H, 2W, C)
+__global__ void k_up_fwd(const float* __restrict__ in, int B, int H, int W, int C, float* __restrict__ out) {
+    const long long n = (long long)B * 2 * H * 2 * W * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        long long r = i / C;
+        const int x = (int)(r % (2 * W));
+        r /= (2 * W);
+        const int y = (int)(r % (2 * H));
+        const int b = (int)(r / (2 * H));
+        out[i] = in[(((long long)b * H + y / 2) * W + x / 2) * C + c];
+    }
+}
+__global__ void k_up_bwd(const float* __restrict__ dout, int B, int H, int W, int C, float* __restrict__ din) {
+    const long long n = (long long)B * H * W * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        long long r = i / C;
+        const int x = (int)(r % W);
+        r /= W;
+        const int y = (int)(r % H);
+        const int b = (int)(r / H);
+        const long long W2 = 2LL * W;
+        const float* s = dout + (((long long)b * 2 * H + 2 * y) * W2 + 2 * x) * C + c;
+        din[i] = s[0] + s[C] + s[W2 * C] + s[W2 * C + C];
+    }
+}
+// channel concatenation [a | b] and its split, P pixels
+__global__ void k_concat(const float* __restrict__ a, int Ca, const float* __restrict__ b, int Cb, long long P,
+                         float* __restrict__ out) {
+    const int C = Ca + Cb;
+    const long long n = P * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long p = i / C;
+        const int c = (int)(i - p * C);
+        out[i] = c < Ca ? a[p * Ca + c] : b[p * Cb + (c - Ca)];
+    }
+}
+__global__ void k_split_add(const float* __restrict__ d, int Ca, int Cb, long long P, float* __restrict__ da,
+                            float* __restrict__ db) {
+    // da = d[:, :Ca] (overwrite), db += d[:, Ca:] (the skip branch already holds a gradient)
+    const int C = Ca + Cb;
+    const long long n = P * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long p = i / C;
+        const int c = (int)(i - p * C);
+        if (c < Ca)
+            da[p * Ca + c] = d[i];
+        else
+            db[p * Cb + (c - Ca)] += d[i];
+    }
+}
+
+// mean squared error over the first Cu of C channels: partial sums per
+// workgroup (FP64) and the gradient 2 (pred - target) / count
+__global__ void k_mse(const float* __restrict__ pred, const float* __restrict__ target, long long P, int C, int Cu,
+                      double* __restrict__ partial, float* __restrict__ dpred) {
+    __shared__ double red[256];
+    const double inv = 1.0 / ((double)P * Cu);
+    double s = 0.0;
+    const long long n = P * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        float g = 0.f;
+        if (c < Cu) {
+            const double d = (double)pred[i] - (double)target[i];
+            s += d * d;
+            g = (float)(2.0 * d * inv);
+        }
+        if (dpred) dpred[i] = g;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] * inv;
+}
+
+// Adam on the FP32 master weights W[tap][ci][co] (n = 9 Cin Cout) and biases,
+// then the two BF16 operand copies Wf[co][tap][ci] and Wd[ci][tap][co]
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long long n, float lr, float b1, float b2, float eps, float c1, float c2,
+                       float wdecay) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wdecay * w[i]);
+    }
+}
+__global__ void k_pack_weights(const float* __restrict__ w, int Cin, int Cout, unsigned short* __restrict__ wf,
+                               unsigned short* __restrict__ wd) {
+    const long long n = 9LL * Cin * Cout;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int co = (int)(i % Cout);
+        const long long r = i / Cout;
+        const int ci = (int)(r % Cin);
+        const int tap = (int)(r / Cin);
+        const unsigned short h = bf16_bits(w[i]);
+        wf[((long long)co * 9 + tap) * Cin + ci] = h;
+        wd[((long long)ci * 9 + tap) * Cout + co] = h;
+    }
+}
+
+// network input from stacked field planes soa[b][f][p] (f < nf): the
+// normalised fields, then nc per-image conditioning values, zero padding to C
+__global__ void k_pack(const float* __restrict__ soa, long long P, int nf, const float* __restrict__ mean,
+                       const float* __restrict__ inv_scale, const float* __restrict__ cond, int nc, int B, int C,
+                       float* __restrict__ out) {
+    const long long n = (long long)B * P * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const long long bp = i / C;
+        const long long p = bp % P;
+        const int b = (int)(bp / P);
+        float v = 0.f;
+        if (c < nf)
+            v = (soa[((long long)b * nf + c) * P + p] - mean[c]) * inv_scale[c];
+        else if (c < nf + nc)
+            v = cond[b * nc + (c - nf)];
+        out[i] = v;
+    }
+}
+// fields after the jump: soa_out[b][f][p] = soa_in[b][f][p] + net[b][p][f] * dscale[f]
+__global__ void k_unpack(const float* __restrict__ soa_in, const float* __restrict__ net, long long P, int nf, int C,
+                         const float* __restrict__ dscale, int B, float* __restrict__ soa_out) {
+    const long long n = (long long)B * nf * P;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long p = i % P;
+        const long long bf = i / P;
+        const int f = (int)(bf % nf);
+        const int b = (int)(bf / nf);
+        soa_out[i] = soa_in[i] + net[((long long)b * P + p) * C + f] * dscale[f];
+    }
+}
+__global__ void k_axpy(const float* __restrict__ x, long long n, float a, float* __restrict__ y) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        y[i] += a * x[i];
+}
+
+__global__ void k_fill(float* __restrict__ p, long long n, float v) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------- launchers
+inline unsigned grid_for(long long n) {
+    long long g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace cno
+
+using namespace cno;
+
+namespace {
+int last_rc(hipError_t e) { return e == hipSuccess ? EELBM_OK : EELBM_E_HIP; }
+
+// pick the number of 16-wide output tiles per wavefront (<= kMaxNT) and the
+// grid's y extent
+void tiles(int Cout, int* nt, int* gy) {
+    const int tiles16 = Cout / 16;
+    int best = 1;
+    for (int d = 1; d <= kMaxNT; ++d)
+        if (tiles16 % d == 0) best = d;
+    *nt = best;
+    *gy = tiles16 / best;
+}
+
+template <int NT>
+void fwd_nt(const float* in, int B, int H, int W, int Cin, const unsigned short* wf, const float* bias, int Cout,
+            float* out, int act, float slope, dim3 g, hipStream_t s) {
+    hipLaunchKernelGGL((k_conv_fwd<NT>), g, dim3(64), 0, s, in, B, H, W, Cin, wf, bias, Cout, out, act, slope);
+}
+template <int NT>
+void bwd_nt(const float* dout, int B, int H, int W, int Cout, const unsigned short* wd, int Cin, float* din, dim3 g,
+            hipStream_t s) {
+    hipLaunchKernelGGL((k_conv_bwd_data<NT>), g, dim3(64), 0, s, dout, B, H, W, Cout, wd, Cin, din);
+}
+
+bool shape_ok(int B, int H, int W, int Cin, int Cout) {
+    return B > 0 && H > 0 && W > 0 && Cin > 0 && Cout > 0 && Cin % 16 == 0 && Cout % 16 == 0 && Cout <= 16 * 16 * 12 &&
+           Cin <= 4096 && Cout <= 4096;
+}
+}  // namespace
+
+extern "C" {
+
+int eelbm_cno_conv_fwd(const float* in, int32_t B, int32_t H, int32_t W, int32_t Cin, const uint16_t* wf,
+                       const float* bias, int32_t Cout, float* out, int32_t act, float slope, void* stream) {
+    if (!in || !wf || !out || !shape_ok(B, H, W, Cin, Cout)) return EELBM_E_PARAM;
+    int nt, gy;
+    tiles(Cout, &nt, &gy);
+    const dim3 g((unsigned)((long long)B * H * ((W + 15) / 16)), (unsigned)gy);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (nt) {
+#define CASE(N) \
+    case N: fwd_nt<N>(in, B, H, W, Cin, wf, bias, Cout, out, act, slope, g, s); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12)
+#undef CASE
+        default: return EELBM_E_PARAM;
+    }
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_conv_bwd_data(const float* dout, int32_t B, int32_t H, int32_t W, int32_t Cout, const uint16_t* wd,
+                            int32_t Cin, float* din, void* stream) {
+    if (!dout || !wd || !din || !shape_ok(B, H, W, Cout, Cin)) return EELBM_E_PARAM;
+    int nt, gy;
+    tiles(Cin, &nt, &gy);
+    const dim3 g((unsigned)((long long)B * H * ((W + 15) / 16)), (unsigned)gy);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (nt) {
+#define CASE(N) \
+    case N: bwd_nt<N>(dout, B, H, W, Cout, wd, Cin, din, g, s); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12)
+#undef CASE
+        default: return EELBM_E_PARAM;
+    }
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_conv_bwd_weight(const float* in, const float* dout, int32_t B, int32_t H, int32_t W, int32_t Cin,
+                              int32_t Cout, float* dw, float* dbias, void* stream) {
+    if (!in || !dout || !dw || !shape_ok(B, H, W, Cin, Cout) || Cout > 256) return EELBM_E_PARAM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long long P = (long long)B * H * W;
+    const int chunk = 2048;
+    const long long nk = (P + chunk - 1) / chunk;
+    if (nk > 65535) return EELBM_E_PARAM;
+    hipLaunchKernelGGL(k_conv_bwd_weight, dim3((unsigned)(9 * Cin / 16), (unsigned)(Cout / 16), (unsigned)nk),
+                       dim3(64), 0, s, in, dout, B, H, W, Cin, Cout, chunk, dw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return EELBM_E_HIP;
+    if (dbias) {
+        hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, dout, P, Cout, dbias);
+        e = hipGetLastError();
+    }
+    return last_rc(e);
+}
+
+int eelbm_cno_act_bwd(const float* y, const float* dy, int64_t n, float slope, float* dx, void* stream) {
+    if (!y || !dy || !dx || n < 0) return EELBM_E_PARAM;
+    hipLaunchKernelGGL(k_act_bwd, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), y, dy, n, slope,
+                       dx);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_pool(const float* in, int32_t B, int32_t H, int32_t W, int32_t C, float* out, int32_t backward,
+                   void* stream) {
+    if (!in || !out || B < 1 || H < 2 || W < 2 || C < 1 || (H & 1) || (W & 1)) return EELBM_E_PARAM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (backward)
+        hipLaunchKernelGGL(k_pool_bwd, dim3(grid_for((long long)B * H * W * C)), dim3(256), 0, s, in, B, H, W, C, out);
+    else
+        hipLaunchKernelGGL(k_pool_fwd, dim3(grid_for((long long)B * H * W * C / 4)), dim3(256), 0, s, in, B, H, W, C,
+                           out);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_up(const float* in, int32_t B, int32_t H, int32_t W, int32_t C, float* out, int32_t backward,
+                 void* stream) {
+    if (!in || !out || B < 1 || H < 1 || W < 1 || C < 1) return EELBM_E_PARAM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // forward: (H, W) -> (2H, 2W); backward: gradient of (2H, 2W) -> (H, W)
+    if (backward)
+        hipLaunchKernelGGL(k_up_bwd, dim3(grid_for((long long)B * H * W * C)), dim3(256), 0, s, in, B, H, W, C, out);
+    else
+        hipLaunchKernelGGL(k_up_fwd, dim3(grid_for((long long)B * 4 * H * W * C)), dim3(256), 0, s, in, B, H, W, C,
+                           out);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_concat(const float* a, int32_t Ca, const float* b, int32_t Cb, int64_t P, float* out, void* stream) {
+    if (!a || !b || !out || Ca < 1 || Cb < 1 || P < 1) return EELBM_E_PARAM;
+    hipLaunchKernelGGL(k_concat, dim3(grid_for(P * (Ca + Cb))), dim3(256), 0, static_cast<hipStream_t>(stream), a, Ca,
+                       b, Cb, P, out);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_split_add(const float* d, int32_t Ca, int32_t Cb, int64_t P, float* da, float* db, void* stream) {
+    if (!d || !da || !db || Ca < 1 || Cb < 1 || P < 1) return EELBM_E_PARAM;
+    hipLaunchKernelGGL(k_split_add, dim3(grid_for(P * (Ca + Cb))), dim3(256), 0, static_cast<hipStream_t>(stream), d,
+                       Ca, Cb, P, da, db);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_mse(const float* pred, const float* target, int64_t P, int32_t C, int32_t Cused, double* partial,
+                  int32_t nblocks, float* dpred, void* stream) {
+    if (!pred || !target || !partial || P < 1 || C < 1 || Cused < 1 || Cused > C || nblocks < 1) return EELBM_E_PARAM;
+    hipLaunchKernelGGL(k_mse, dim3(nblocks), dim3(256), 0, static_cast<hipStream_t>(stream), pred, target, P, C, Cused,
+                       partial, dpred);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                   int64_t step, float weight_decay, void* stream) {
+    if (!w || !g || !m || !v || n < 1 || step < 1) return EELBM_E_PARAM;
+    const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), w, g, m, v, n, lr, b1,
+                       b2, eps, c1, c2, weight_decay);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_pack_weights(const float* w, int32_t Cin, int32_t Cout, uint16_t* wf, uint16_t* wd, void* stream) {
+    if (!w || !wf || !wd || Cin < 1 || Cout < 1) return EELBM_E_PARAM;
+    hipLaunchKernelGGL(k_pack_weights, dim3(grid_for(9LL * Cin * Cout)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), w, Cin, Cout, wf, wd);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_pack(const float* soa, int64_t P, int32_t nf, const float* mean, const float* inv_scale,
+                   const float* cond, int32_t nc, int32_t B, int32_t C, float* out, void* stream) {
+    if (!soa || !mean || !inv_scale || !out || (nc > 0 && !cond) || P < 1 || nf < 1 || nc < 0 || B < 1 ||
+        nf + nc > C)
+        return EELBM_E_PARAM;
+    hipLaunchKernelGGL(k_pack, dim3(grid_for((long long)B * P * C)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       soa, P, nf, mean, inv_scale, cond, nc, B, C, out);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_unpack(const float* soa_in, const float* net, int64_t P, int32_t nf, int32_t C, const float* dscale,
+                     int32_t B, float* soa_out, void* stream) {
+    if (!soa_in || !net || !dscale || !soa_out || P < 1 || nf < 1 || nf > C || B < 1) return EELBM_E_PARAM;
+    hipLaunchKernelGGL(k_unpack, dim3(grid_for((long long)B * nf * P)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), soa_in, net, P, nf, C, dscale, B, soa_out);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_axpy(const float* x, int64_t n, float a, float* y, void* stream) {
+    if (!x || !y || n < 0) return EELBM_E_PARAM;
+    if (n == 0) return EELBM_OK;
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), x, n, a, y);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_fill(float* p, int64_t n, float value, void* stream) {
+    if (!p || n < 0) return EELBM_E_PARAM;
+    if (n == 0) return EELBM_OK;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), p, n, value);
+    return last_rc(hipGetLastError());
+}
+
+}  // extern "C"

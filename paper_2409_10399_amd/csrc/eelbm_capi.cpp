@@ -304,8 +304,9 @@ int launch(eelbm_handle* h, bool init, int64_t t, bool last) {
     c.refresh = (t % h->p.n_gamma) == 0;
     c.write_macro = last;
     c.write_diag = last;
-    const int in = init ? 1 : h->cur;
-    const int out = init ? 0 : 1 - h->cur;
+    // the state at time t is always copy t mod 2
+    const int in = init ? 1 - (int)(t & 1) : h->cur;
+    const int out = init ? (int)(t & 1) : 1 - h->cur;
     KBuffers b = buffers(h, in, out);
     hipError_t e = launch_step(h->p.lattice, h->p.storage, h->g.channel, init, h->kp, b, c, h->g.grid, h->g.block,
                                h->stream);
@@ -371,10 +372,17 @@ int eelbm_create(const eelbm_params* p, void* device_mem, size_t bytes, void* hi
     return EELBM_OK;
 }
 
-int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g, const double* u_l,
-                      const double* dp_k, const double* inlet_noise, int on_device) {
+}  // extern "C"
+
+namespace {
+// initial state (keep = false) or rebuilt state at time t (keep = true:
+// inlet noise, buoyancy reference and lag fields are those of the run)
+int init_impl(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u_g, const double* u_l,
+              const double* dp_k, const double* inlet_noise, int on_device, bool keep) {
     if (!h) return fail(EELBM_E_PARAM, "handle is NULL");
     if (!alpha_g) return fail(EELBM_E_PARAM, "alpha_g is NULL");
+    if (keep && !h->initialized) return fail(EELBM_E_STATE, "eelbm_init_fields not called");
+    if (t < 0) return fail(EELBM_E_PARAM, "t < 0");
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     const size_t n = (size_t)h->g.n;
@@ -394,7 +402,7 @@ int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g,
         }
         if (rc) return rc;
     }
-    if (h->g.face_n > 0) {
+    if (h->g.face_n > 0 && !keep) {
         double* noise = reinterpret_cast<double*>(h->mem + h->L.noise);
         if (inlet_noise) {
             rc = copy_in(h, noise, inlet_noise, (size_t)h->g.face_n * 8, on_device);
@@ -426,7 +434,9 @@ int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g,
     }
     if (!std::isfinite(am)) return fail(EELBM_E_NONFINITE, "non-finite initial gas fraction");
     h->alpha_ref = p.storage == EELBM_FP64 ? am : (double)(float)am;
-    if (p.rho_ref_mode == EELBM_RHOREF_LIQUID) {
+    if (keep) {
+        // buoyancy reference of the run
+    } else if (p.rho_ref_mode == EELBM_RHOREF_LIQUID) {
         h->rho_ref = p.rho_l;
     } else if (p.rho_ref_mode == EELBM_RHOREF_EXPLICIT) {
         h->rho_ref = p.rho_ref;
@@ -436,7 +446,7 @@ int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g,
     h->b_g = (h->rho_ref / p.rho_g - 1.0) * p.g_hat;
     h->b_l = (h->rho_ref / p.rho_l - 1.0) * p.g_hat;
     fill_kparams(h);
-    rc = launch(h, true, 0, true);
+    rc = launch(h, true, t, true);
     if (rc) return rc;
     if (!on_device) {
         // host inputs were copied from pageable memory; finish before returning
@@ -445,6 +455,19 @@ int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g,
     }
     h->initialized = true;
     return EELBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g, const double* u_l,
+                      const double* dp_k, const double* inlet_noise, int on_device) {
+    return init_impl(h, 0, alpha_g, u_g, u_l, dp_k, inlet_noise, on_device, false);
+}
+
+int eelbm_reinit_fields(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u_g, const double* u_l,
+                        const double* dp_k, int on_device) {
+    return init_impl(h, t, alpha_g, u_g, u_l, dp_k, nullptr, on_device, true);
 }
 
 int eelbm_advance(eelbm_handle* h, int64_t nsteps) {
