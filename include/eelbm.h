@@ -193,9 +193,10 @@ int eelbm_diag(eelbm_handle* h, eelbm_diagnostics* out);
 int64_t eelbm_time(const eelbm_handle* h);
 
 /* Launch shape of the step kernel (for tuning; results do not depend on it):
- * one workgroup per tile of tile_x * tile_y nodes of an (x, y) plane, a whole
- * number of 64-wide wavefronts and at most 256 nodes; xcd_remap = 1 hands each
- * of the 8 XCDs one contiguous run of tiles.  The diagnostics of the last
+ * one workgroup per tile of tile_x * tile_y nodes of an (x, y) plane, tile_x
+ * a multiple of 64 (a wavefront is one 64-node x-block of the population
+ * layout) and tile_x * tile_y at most 256; xcd_remap = 1 hands each of the 8
+ * XCDs one contiguous run of tiles.  EELBM_E_PARAM otherwise.  The diagnostics of the last
  * step refer to the shape they were produced with, so call this before
  * eelbm_advance. */
 int eelbm_set_launch(eelbm_handle* h, int32_t tile_x, int32_t tile_y, int32_t xcd_remap);
@@ -326,10 +327,10 @@ int eelbm_cno_adam(float* w, const float* g, float* m, float* v, int64_t n, floa
 /* BF16 operand copies Wf and Wd of the FP32 master W (9 Cin Cout values). */
 int eelbm_cno_pack_weights(const float* w, int32_t Cin, int32_t Cout, uint16_t* wf, uint16_t* wd, void* stream);
 /* Network input: out[b][p][c] = (soa[b][c][p] - mean[c]) * inv_scale[c] for
- * c < nf (stacked field planes, P pixels per image), cond[b][c - nf] for
- * nf <= c < nf + nc, 0 up to C. */
+ * c < nf (stacked field planes, P pixels per image; clamped to [-clip, clip]
+ * if clip > 0), cond[b][c - nf] for nf <= c < nf + nc, 0 up to C. */
 int eelbm_cno_pack(const float* soa, int64_t P, int32_t nf, const float* mean, const float* inv_scale,
-                   const float* cond, int32_t nc, int32_t B, int32_t C, float* out, void* stream);
+                   const float* cond, int32_t nc, int32_t B, int32_t C, float clip, float* out, void* stream);
 /* Fields after a jump: soa_out[b][f][p] = soa_in[b][f][p] + net[b][p][f] * dscale[f], f < nf. */
 int eelbm_cno_unpack(const float* soa_in, const float* net, int64_t P, int32_t nf, int32_t C, const float* dscale,
                      int32_t B, float* soa_out, void* stream);

@@ -91,7 +91,7 @@ SYMBOLS = {
                                ctypes.c_float, ctypes.c_float, c_int64, ctypes.c_float, c_void_p]),
     "eelbm_cno_pack_weights": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "eelbm_cno_pack": (c_int, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32,
-                               c_void_p, c_void_p]),
+                               ctypes.c_float, c_void_p, c_void_p]),
     "eelbm_cno_unpack": (c_int, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int32, c_void_p,
                                  c_void_p]),
     "eelbm_cno_axpy": (c_int, [c_void_p, c_int64, ctypes.c_float, c_void_p, c_void_p]),

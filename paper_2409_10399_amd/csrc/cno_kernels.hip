@@ -355,7 +355,7 @@ __global__ void k_pack_weights(const float* __restrict__ w, int Cin, int Cout, u
 // normalised fields, then nc per-image conditioning values, zero padding to C
 __global__ void k_pack(const float* __restrict__ soa, long long P, int nf, const float* __restrict__ mean,
                        const float* __restrict__ inv_scale, const float* __restrict__ cond, int nc, int B, int C,
-                       float* __restrict__ out) {
+                       float clip, float* __restrict__ out) {
     const long long n = (long long)B * P * C;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const int c = (int)(i % C);
@@ -363,8 +363,10 @@ __global__ void k_pack(const float* __restrict__ soa, long long P, int nf, const
         const long long p = bp % P;
         const int b = (int)(bp / P);
         float v = 0.f;
-        if (c < nf)
+        if (c < nf) {
             v = (soa[((long long)b * nf + c) * P + p] - mean[c]) * inv_scale[c];
+            if (clip > 0.f) v = fminf(fmaxf(v, -clip), clip);
+        }
         else if (c < nf + nc)
             v = cond[b * nc + (c - nf)];
         out[i] = v;
@@ -560,12 +562,12 @@ int eelbm_cno_pack_weights(const float* w, int32_t Cin, int32_t Cout, uint16_t* 
 }
 
 int eelbm_cno_pack(const float* soa, int64_t P, int32_t nf, const float* mean, const float* inv_scale,
-                   const float* cond, int32_t nc, int32_t B, int32_t C, float* out, void* stream) {
+                   const float* cond, int32_t nc, int32_t B, int32_t C, float clip, float* out, void* stream) {
     if (!soa || !mean || !inv_scale || !out || (nc > 0 && !cond) || P < 1 || nf < 1 || nc < 0 || B < 1 ||
         nf + nc > C)
         return EELBM_E_PARAM;
     hipLaunchKernelGGL(k_pack, dim3(grid_for((long long)B * P * C)), dim3(256), 0, static_cast<hipStream_t>(stream),
-                       soa, P, nf, mean, inv_scale, cond, nc, B, C, out);
+                       soa, P, nf, mean, inv_scale, cond, nc, B, C, clip, out);
     return last_rc(hipGetLastError());
 }
 

@@ -239,14 +239,15 @@ class CNO:
         self.repack()
 
 
-def pack_input(fields, mean, inv_scale, cond, C):
+def pack_input(fields, mean, inv_scale, cond, C, clip=8.0):
     """fields: (B, 6, H, W) FP32 device tensor of FIELD_PLANES; cond (B, nc);
-    returns the (B, H, W, C) network input."""
+    returns the (B, H, W, C) network input (normalised fields clamped to
+    +-clip)."""
     import torch
     B, nf, H, W = fields.shape
     out = torch.empty((B, H, W, C), dtype=torch.float32, device="cuda")
     _check(lib().eelbm_cno_pack(_p(fields), H * W, nf, _p(mean), _p(inv_scale), _p(cond), cond.shape[1], B, C,
-                                _p(out), _stream()))
+                                float(clip), _p(out), _stream()))
     return out
 
 

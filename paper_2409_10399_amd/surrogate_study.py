@@ -104,7 +104,7 @@ class Normaliser:
     deviation of the change over `lag` snapshots (field by field: the
     snapshot tensor is tens of GB)."""
 
-    def __init__(self, snaps, lag, keep):
+    def __init__(self, snaps, lag, keep, alpha_weight=1.0):
         import torch
         mean, scale, dscale = [], [], []
         idx = torch.tensor(keep, device="cuda")
@@ -114,13 +114,22 @@ class Normaliser:
             scale.append(float(x.std()))
             dscale.append(float((x[lag:] - x[:-lag]).std()))
             del x
+        dscale[0] /= alpha_weight  # the judged field weighs alpha_weight^2 in the loss
+        self.outliers = []
+        for c in range(6):
+            x = snaps[:, :, c].index_select(1, idx)
+            self.outliers.append([float(((x - mean[c]) / scale[c]).abs().amax()),
+                                  float(((x[lag:] - x[:-lag]) / dscale[c]).abs().amax())])
+            del x
         t = lambda v: torch.tensor(v, dtype=torch.float32, device="cuda")
         self.mean, self.scale, self.dscale = t(mean), t(scale).clamp_min(1e-12), t(dscale).clamp_min(1e-12)
         self.inv, self.dinv = 1.0 / self.scale, 1.0 / self.dscale
         self.zero = torch.zeros(6, dtype=torch.float32, device="cuda")
 
     def as_dict(self):
-        return {k: getattr(self, k).tolist() for k in ("mean", "scale", "dscale")}
+        d = {k: getattr(self, k).tolist() for k in ("mean", "scale", "dscale")}
+        d["max_abs_normalised_field_and_change"] = self.outliers
+        return d
 
 
 def defect(f0, f1, jump):
@@ -136,7 +145,11 @@ def defect(f0, f1, jump):
     return ((vol1 - vol0 - budget).abs() / vol0.abs()).double().cpu().numpy()
 
 
-def train(net, snaps, cond, norm, lag, epochs, bsz, lr, log, keep):
+def train(net, snaps, cond, norm, lag, epochs, bsz, lr, log, keep, noise=0.0):
+    """Adam with cosine decay on random pairs; noise > 0 adds Gaussian noise
+    of that standard deviation (normalised units) to the input fields, so
+    that the network learns to correct perturbed states such as its own
+    earlier predictions."""
     import torch
     from paper_2409_10399_amd.binding import lib
     from paper_2409_10399_amd.surrogate import _p, _stream, pack_input
@@ -158,8 +171,12 @@ def train(net, snaps, cond, norm, lag, epochs, bsz, lr, log, keep):
             f1 = torch.stack([snaps[s + lag, i] for s, i in idx]).contiguous()
             c = torch.stack([cond[i] for _, i in idx]).contiguous()
             x = pack_input(f0, norm.mean, norm.inv, c, net.cin)
-            tgt = pack_input(f1, norm.zero, norm.dinv, c[:, :0].contiguous(), net.cout)
-            tp = pack_input(f0, norm.zero, norm.dinv, c[:, :0].contiguous(), net.cout)
+            if noise > 0:
+                eps = torch.zeros_like(x)
+                eps[..., :6].normal_(0.0, noise)
+                _check_rc(L.eelbm_cno_axpy(_p(eps), x.numel(), 1.0, _p(x), _stream()))
+            tgt = pack_input(f1, norm.zero, norm.dinv, c[:, :0].contiguous(), net.cout, clip=0.0)
+            tp = pack_input(f0, norm.zero, norm.dinv, c[:, :0].contiguous(), net.cout, clip=0.0)
             _check_rc(L.eelbm_cno_axpy(_p(tp), tgt.numel(), -1.0, _p(tgt), _stream()))
             # cosine learning-rate decay
             rate = lr * 0.5 * (1.0 + math.cos(math.pi * it / total))
@@ -182,6 +199,7 @@ def _check_rc(rc):
 def rollout(net, lats, inst, cond, norm, t0, jumps, jump, defect_max, check_every, log):
     """Surrogate rollout of all lattices together from their LBM state at t0."""
     import torch
+    from paper_2409_10399_amd import Batch
     from paper_2409_10399_amd.surrogate import apply_output, pack_input
     N = len(lats)
     ny, nx = inst[0][0]["ny"], inst[0][0]["nx"]
@@ -200,14 +218,16 @@ def rollout(net, lats, inst, cond, norm, t0, jumps, jump, defect_max, check_ever
         force = check_every > 0 and (j + 1) % check_every == 0
         bad = np.where((dfc > defect_max) | ~np.isfinite(dfc) | force)[0]
         for i in bad:
-            lat = lats[i]
             if not valid[i]:
                 fi = f[i].double()
-                lat.reinit_fields_device(t, {"alpha_g": fi[0].contiguous(), "u_g": fi[1:3].contiguous(),
-                                             "u_l": fi[3:5].contiguous(), "dp_k": fi[5].contiguous()})
-            lat.advance(jump)
-            read_fields(lat, pred[i])
-            anchors += 1
+                lats[i].reinit_fields_device(t, {"alpha_g": fi[0].contiguous(), "u_g": fi[1:3].contiguous(),
+                                                 "u_l": fi[3:5].contiguous(), "dp_k": fi[5].contiguous()})
+        if len(bad):
+            # the re-anchored lattices advance together, one launch per step
+            Batch([lats[i] for i in bad], tile=(64, 4)).advance(jump)
+            for i in bad:
+                read_fields(lats[i], pred[i])
+            anchors += len(bad)
         valid[:] = False
         valid[bad] = True
         f = pred
@@ -226,7 +246,9 @@ def main():
     ap.add_argument("--snap", type=int, default=50)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--batch", type=int, default=8)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=5e-4)
+    ap.add_argument("--alpha-weight", type=float, default=3.0)
+    ap.add_argument("--noise", type=float, default=0.0)
     ap.add_argument("--widths", default="32,48,96,192")
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--defect-max", type=float, default=1.5e-2)
@@ -254,8 +276,9 @@ def main():
     keep = stable_members(snaps)
     report["train_members_kept"] = len(keep)
     log(f"# {len(keep)} of {a.train_inst} channels stay finite with |u| < 0.1 up to t = {t_end}")
-    norm = Normaliser(snaps, lag, keep)
+    norm = Normaliser(snaps, lag, keep, a.alpha_weight)
     report["normaliser"] = norm.as_dict()
+    log(f"# max |normalised| (field, change) per plane: {[[round(v, 1) for v in o] for o in norm.outliers]}")
     # plain LBM's own conservation defect over single jumps (calibrates defect_max)
     lbm_def = np.concatenate([defect(snaps[s][keep], snaps[s + lag][keep], a.jump) for s in range(snaps.shape[0] - lag)])
     report["lbm_defect_percentiles_50_99_max"] = [float(np.percentile(lbm_def, 50)), float(np.percentile(lbm_def, 99)),
@@ -266,7 +289,7 @@ def main():
     net = CNO(9, 6, [int(w) for w in a.widths.split(",")], seed=0)
     log(f"# network: widths {net.widths}, {net.n_params} parameters; {snaps.shape[0] - lag} x {a.train_inst} pairs")
     T = time.time()
-    report["loss_history"] = train(net, snaps, cond, norm, lag, a.epochs, a.batch, a.lr, log, keep)
+    report["loss_history"] = train(net, snaps, cond, norm, lag, a.epochs, a.batch, a.lr, log, keep, a.noise)
     report["train_seconds"] = time.time() - T
     del snaps
     torch.cuda.empty_cache()
