@@ -200,6 +200,25 @@ __device__ __forceinline__ X* at(X* base, unsigned byte_off) {
     return reinterpret_cast<X*>(reinterpret_cast<char*>(base) + byte_off);
 }
 
+// reciprocal and square root of the compute type: the hardware's
+// single-instruction forms (1 ulp) in FP32, correctly rounded in FP64
+template <class C>
+__device__ __forceinline__ C rcp(C v) {
+    return C(1) / v;
+}
+template <>
+__device__ __forceinline__ float rcp<float>(float v) {
+    return __builtin_amdgcn_rcpf(v);
+}
+template <class C>
+__device__ __forceinline__ C root(C v) {
+    return sqrt(v);
+}
+template <>
+__device__ __forceinline__ float root<float>(float v) {
+    return __builtin_amdgcn_sqrtf(v);
+}
+
 template <class C>
 __device__ __forceinline__ C clamp01(C v) {
     return v < C(0) ? C(0) : (v > C(1) ? C(1) : v);
@@ -649,13 +668,13 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                 // B is the identity: alpha_g = a_g / (a_g + a_l), written around
                 // a_g + a_l = 1 so that FP32 keeps the small correction exactly
                 const C e = sag + sal;  // a_g + a_l - 1
-                const C corr = ag * e / (C(1) + e);
+                const C corr = ag * e * rcp(C(1) + e);
                 alg = ag - corr;
                 dag = sag - corr;
             } else {
                 const C Bg = clamp01(ag), Bl = clamp01(al_raw);
                 const C den = Bg + Bl;
-                alg = den > C(0) ? Bg / den : C(0);
+                alg = den > C(0) ? Bg * rcp(den) : C(0);
                 dag = alg - ar;
             }
             all = C(1) - alg;
@@ -734,11 +753,11 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
             du[a] = ul[a] - ug[a];
             dun2 += du[a] * du[a];
         }
-        const C dun = sqrt(dun2);
-        const C uln = sqrt(usl);
+        const C dun = root(dun2);
+        const C uln = root(usl);
         const C K = p.cgw ? C(p.kappa_I) * Laml : C(p.K_I);
         C Gg[D], Gl[D];
-        const C inv_agf = C(1) / agf, inv_alfR = C(1) / (alf * R);
+        const C inv_agf = rcp(agf), inv_alf = rcp(alf), inv_alfR = inv_alf * invR;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             C sgg = C(0), sgl = C(0);
@@ -749,7 +768,7 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                     sgl -= sl[sym<D>(a, bb)] * grad[bb];
                 }
                 sgg = sgg * inv_agf;
-                sgl = sgl / alf;
+                sgl = sgl * inv_alf;
             }
             const C bg = a == p.up ? C(p.b_g) : C(0);
             const C bl = a == p.up ? C(p.b_l) : C(0);
@@ -765,28 +784,39 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
         const long long oblk = ((long long)y * p.nxb + (x >> 6)) * kBlk;
         const unsigned vl = (unsigned)((x & 63) * 4 * (int)sizeof(T));
         {
+            // BGK relaxation plus forcing, f + omega (f^eq - f) + f^L, regrouped
+            // as (1 - omega) f + w_q [A + omega s(c.u) + 3 c.G] with the
+            // node constants A hoisted out of the direction loop and
+            // s(x) = 3 x + 9/2 x^2 shared by the two sets of a phase
             const C w0 = C(L::w[0]);
             const C k0 = (C(1) - w0) / w0;
             const C el0 = del + k0 * (del - dphiel);  // eps_l eta_0(phi) - 1, Eq. (38)
             const C eg0 = C(1) + k0 * (C(1) - C(p.psi_g));
             const C el0p = C(1) + k0 * (C(1) - C(p.psi_l));
             const C og = C(p.omega_g), ol = C(p.omega_l), oag = C(p.omega_ag), oal = C(p.omega_al);
+            const C kog = C(1) - og, kol = C(1) - ol, koa = C(1) - oag, kob = C(1) - oal;
+            // Eq. (37) with phi = 1 (gas) and phi of Eq. (32) (liquid), Eq. (42)
+            const C bg = og * (deg - C(1.5) * usg), bl = ol * (dphiel - C(1.5) * usl);
+            const C Ag = bg + S2g * C(p.psi_g), Ag0 = bg + S2g * eg0;
+            const C Al = bl + S2l * C(p.psi_l), Al0 = ol * (el0 - C(1.5) * usl) + S2l * el0p;
+            // Eq. (72) for the two volume-fraction schemes
+            const C Aa = oag * (dag - C(1.5) * alg * usg), Ba = oag * alg;
+            const C Ab = oal * (dal - C(1.5) * all * usl), Bb = oal * all;
+            C G3g[D], G3l[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                G3g[a] = C(3) * Gg[a];
+                G3l[a] = C(3) * Gl[a];
+            }
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const C wq = C(L::w[q]);
                 const C cug = dotc<L>(q, ug), cul = dotc<L>(q, ul);
-                const C cGg = dotc<L>(q, Gg), cGl = dotc<L>(q, Gl);
-                const C pg = poly2(cug, usg), pl = poly2(cul, usl);
-                const C feqg = wq * (deg + pg);                               // Eq. (37), phi = 1
-                const C feql = wq * ((q == 0 ? el0 : dphiel) + pl);           // Eq. (37), phi of Eq. (32)
-                const C fLg = wq * (S2g * (q == 0 ? eg0 : C(p.psi_g)) + C(3) * cGg);  // Eq. (42)
-                const C fLl = wq * (S2l * (q == 0 ? el0p : C(p.psi_l)) + C(3) * cGl);
-                const C feqa = wq * (dag + alg * pg);                         // Eq. (72)
-                const C feqb = wq * (dal + all * pl);
-                const C o0 = f[0][q] + og * (feqg - f[0][q]) + fLg;
-                const C o1 = f[1][q] + ol * (feql - f[1][q]) + fLl;
-                const C o2 = f[2][q] + oag * (feqa - f[2][q]);
-                const C o3 = f[3][q] + oal * (feqb - f[3][q]);
+                const C sg2 = cug * (C(3) + C(4.5) * cug), sl2 = cul * (C(3) + C(4.5) * cul);
+                const C o0 = kog * f[0][q] + wq * ((q == 0 ? Ag0 : Ag) + og * sg2 + dotc<L>(q, G3g));
+                const C o1 = kol * f[1][q] + wq * ((q == 0 ? Al0 : Al) + ol * sl2 + dotc<L>(q, G3l));
+                const C o2 = koa * f[2][q] + wq * (Aa + Ba * sg2);
+                const C o3 = kob * f[3][q] + wq * (Ab + Bb * sl2);
                 const C o4[4] = {o0, o1, o2, o3};
                 Pop4<T>::st(ro, vl, (unsigned)((oblk + q * 256) * (long long)sizeof(T)), o4);
             }

@@ -424,16 +424,48 @@ def test_fp32_storage_floor_on_box():
     velocity part of the deviations there, so its error is set by storage
     alone; the GPU bound for that field is derived from this number."""
     cfg, f = workloads.periodic_box_2d()
+    err = _fp32_storage_floor(cfg, f, 1000)
+    assert err["alpha_g"] < 1e-8 and err["u_g"] < 1e-6 and err["u_l"] < 1e-6
+    assert 5e-6 < err["dp_k"] < 5e-5, err
+
+
+def _fp32_storage_floor(cfg, f, steps):
+    """rel-L2 per field of the oracle with its stored deviations rounded to
+    FP32 after every step, against the plain oracle."""
     ref, em = Oracle(cfg, f), Oracle(cfg, f)
-    w = ref.lat.w.reshape((-1, 1, 1))
+    w = ref.lat.w.reshape((-1,) + (1,) * (ref.f["g"].ndim - 1))
     ar = float(np.mean(f["alpha_g"]))
     bases = (("g", w), ("l", w), ("ag", w * ar), ("al", w * (1 - ar)))
-    for _ in range(1000):
+    for _ in range(steps):
         ref.step(1)
         em.step(1)
         for s, base in bases:
             em.f[s] = base + (em.f[s] - base).astype(np.float32).astype(np.float64)
     ro, re = ref.read(), em.read()
-    err = {k: np.linalg.norm(re[k] - ro[k]) / np.linalg.norm(ro[k]) for k in ("alpha_g", "u_g", "u_l", "dp_k")}
-    assert err["alpha_g"] < 1e-8 and err["u_g"] < 1e-6 and err["u_l"] < 1e-6
-    assert 5e-6 < err["dp_k"] < 5e-5, err
+    return {k: np.linalg.norm(re[k] - ro[k]) / np.linalg.norm(ro[k]) for k in ("alpha_g", "u_g", "u_l", "dp_k")}
+
+
+def test_fp32_storage_floor_d3q19_periodic():
+    """The same floor for the D3Q19 periodic boxes of the GPU parity tests
+    (60 steps): delta p_k is again set by storage alone, 3e-6 to 5e-6."""
+    n = 12
+    cfg = workloads._base("D3Q19", nx=n, ny=n + 2, nz=n + 1, rho_l=5.0, drag="cgw", kappa_I=1e-3,
+                          g_hat=1e-5, rho_ref="mixture_mean", gamma=0.5, n_gamma=3, psi_g=0.1, psi_l=0.05,
+                          up_axis=2)
+    f = {k: _tile3(v, (n + 1, n + 2, n)) for k, v in workloads.smooth_random_3d(n, seed=2).items()}
+    err = _fp32_storage_floor(cfg, f, 60)
+    assert err["u_g"] < 1e-7 and err["u_l"] < 1e-7 and 1e-6 < err["dp_k"] < 5e-6, err
+    nx, ny, nz = 192, 6, 8
+    cfg = workloads._base("D3Q19", nx=nx, ny=ny, nz=nz, rho_l=5.0, drag="cgw", kappa_I=1e-3, g_hat=1e-5,
+                          rho_ref="mixture_mean", gamma=0.5, n_gamma=3, psi_g=0.1, up_axis=2)
+    f = {k: _tile3(v, (nz, ny, nx)) for k, v in workloads.smooth_random_3d(8, seed=6).items()}
+    err = _fp32_storage_floor(cfg, f, 60)
+    assert err["u_g"] < 1e-7 and err["u_l"] < 1e-7 and 1e-6 < err["dp_k"] < 5e-6, err
+
+
+def _tile3(v, shape):
+    """Tile a periodic (..., n, n, n) field to (..., nz, ny, nx) by wrapping."""
+    iz = np.arange(shape[0]) % v.shape[-3]
+    iy = np.arange(shape[1]) % v.shape[-2]
+    ix = np.arange(shape[2]) % v.shape[-1]
+    return np.ascontiguousarray(v[..., iz[:, None, None], iy[None, :, None], ix[None, None, :]])
