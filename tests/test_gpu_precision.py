@@ -44,8 +44,11 @@ def _check(cfg, f, steps, table):
             assert np.isfinite(errs[k]) and errs[k] <= tol[k], (storage, k, errs[k], tol[k])
 
 
-def test_storage_precision_channel():
-    cfg, f = workloads.channel_2d(nx=40, ny=48, n_ramp=100.0)
+@pytest.mark.parametrize("nx,ny", [(40, 48), (320, 40)])
+def test_storage_precision_channel(nx, ny):
+    """(320 x 40 is five x-blocks wide, so its interior blocks take the fast
+    gather in every storage type; the stated bounds are those of 40 x 48.)"""
+    cfg, f = workloads.channel_2d(nx=nx, ny=ny, n_ramp=100.0)
     _check(cfg, f, 1000, CHANNEL)
 
 
