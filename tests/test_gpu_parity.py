@@ -281,3 +281,23 @@ def test_fast_gather_matches_general_bitwise(lattice, storage):
     for k in FIELDS:
         ra, rb = np.roll(a.read(k), 64, axis=-1), b.read(k)
         assert np.array_equal(ra, rb), (k, float(np.max(np.abs(ra - rb))))
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-9), ("fp32", 3e-5)])
+@pytest.mark.parametrize("lattice,nx,omega_g,omega_l", [("D2Q9", 11, 1.5, 0.25), ("D3Q19", 7, 1.0, 0.6)])
+def test_poiseuille_walls_exact(lattice, nx, omega_g, omega_l, storage, tol):
+    """The GPU's wall rule against the closed form directly: the exact steady
+    profile of the BGK scheme with half-way bounce-back walls (both phases,
+    no drag), relative max error 1e-9 in FP64 storage.  FP32 storage: rounding
+    the stored deviations alone leaves the D2Q9 gas profile 2.6e-6 off
+    (test_oracle_scheme.test_fp32_storage_floor_poiseuille), the FP32
+    arithmetic adds about x3; bound 10x the floor, 3e-5."""
+    from closed_forms import poiseuille_case
+    cfg, f, up, exact = poiseuille_case(lattice, nx, omega_g, omega_l)
+    g = run_gpu(cfg, f, 6000, storage)
+    for ph in ("g", "l"):
+        prof = g.read("u_" + ph)[up].reshape(-1, nx)
+        ex = exact(ph)
+        err = np.abs(prof - ex).max() / np.abs(ex).max()
+        print(f"  {lattice} {storage} u_{ph}: rel max error {err:.2e}", flush=True)
+        assert err < tol, (ph, err)

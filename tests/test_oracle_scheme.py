@@ -469,3 +469,44 @@ def _tile3(v, shape):
     iy = np.arange(shape[1]) % v.shape[-2]
     ix = np.arange(shape[2]) % v.shape[-1]
     return np.ascontiguousarray(v[..., iz[:, None, None], iy[None, :, None], ix[None, None, :]])
+
+
+@pytest.mark.parametrize("lattice,nx,omega_g,omega_l", [("D2Q9", 11, 1.5, 0.25), ("D3Q19", 7, 1.0, 0.6)])
+def test_poiseuille_exact_discrete_solution(lattice, nx, omega_g, omega_l):
+    """Wall rule, forcing and BGK relaxation together: both phases of a
+    drag-free channel reach the exact steady profile of the BGK scheme with
+    half-way bounce-back walls (parabola plus the tau-dependent uniform slip),
+    to rounding; a dropped force weight, a wrong wall rule or a wrong
+    viscosity changes the profile at O(1)."""
+    from closed_forms import poiseuille_case
+    cfg, f, up, exact = poiseuille_case(lattice, nx, omega_g, omega_l)
+    o = Oracle(cfg, f)
+    o.step(6000)
+    r = o.read()
+    for ph in ("g", "l"):
+        u = r["u_" + ph]
+        prof = u[up].reshape(-1, nx)
+        ex = exact(ph)
+        assert np.abs(prof - ex).max() < 1e-9 * np.abs(ex).max(), (ph, np.abs(prof - ex).max() / np.abs(ex).max())
+        others = [a for a in range(u.shape[0]) if a != up]
+        assert np.abs(u[others]).max() < 1e-6 * np.abs(ex).max()  # rounding noise only
+
+
+def test_fp32_storage_floor_poiseuille():
+    """FP32 storage floor of the D2Q9 Poiseuille case (gas, tau = 2/3, 6000
+    steps): the oracle with its deviations rounded to FP32 every step stays
+    within 1e-6 .. 5e-6 of the closed form; the GPU bound is derived from it."""
+    from closed_forms import poiseuille_case
+    cfg, f, up, exact = poiseuille_case("D2Q9", 11, 1.5, 0.25)
+    em = Oracle(cfg, f)
+    w = em.lat.w.reshape((-1, 1, 1))
+    ar = float(np.mean(f["alpha_g"]))
+    bases = (("g", w), ("l", w), ("ag", w * ar), ("al", w * (1 - ar)))
+    for _ in range(6000):
+        em.step(1)
+        for s, base in bases:
+            em.f[s] = base + (em.f[s] - base).astype(np.float32).astype(np.float64)
+    prof = em.read()["u_g"][up].reshape(-1, 11)
+    ex = exact("g")
+    err = np.abs(prof - ex).max() / np.abs(ex).max()
+    assert 1e-6 < err < 5e-6, err
