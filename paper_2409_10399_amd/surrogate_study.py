@@ -251,10 +251,13 @@ def main():
     ap.add_argument("--noise", type=float, default=0.0)
     ap.add_argument("--widths", default="32,48,96,192")
     ap.add_argument("--grid", type=int, default=256)
-    ap.add_argument("--defect-max", type=float, default=1.5e-2)
-    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--defect-max", type=float, default=1e-3)
+    ap.add_argument("--check-every", type=int, default=5)
     ap.add_argument("--out", default="")
     ap.add_argument("--save-weights", default="")
+    ap.add_argument("--load-weights", default="", help="weights of --save-weights: skip training")
+    ap.add_argument("--policies", default="",
+                    help="extra re-anchoring policies to judge the same network with, 'defect_max:check_every,...'")
     a = ap.parse_args()
     import torch
     from paper_2409_10399_amd import Batch
@@ -289,7 +292,14 @@ def main():
     net = CNO(9, 6, [int(w) for w in a.widths.split(",")], seed=0)
     log(f"# network: widths {net.widths}, {net.n_params} parameters; {snaps.shape[0] - lag} x {a.train_inst} pairs")
     T = time.time()
-    report["loss_history"] = train(net, snaps, cond, norm, lag, a.epochs, a.batch, a.lr, log, keep, a.noise)
+    if a.load_weights:
+        w = np.load(a.load_weights)
+        arrs = [w["arr_%d" % k] for k in range(len(w.files))]
+        net.set_params(list(zip(arrs[0::2], arrs[1::2])))
+        report["loss_history"] = None
+        log(f"# weights loaded from {a.load_weights}")
+    else:
+        report["loss_history"] = train(net, snaps, cond, norm, lag, a.epochs, a.batch, a.lr, log, keep, a.noise)
     report["train_seconds"] = time.time() - T
     del snaps
     torch.cuda.empty_cache()
@@ -355,6 +365,24 @@ def main():
     log(f"# rel-L2(alpha_g) at t = {t_end}: surrogate max {max(err):.4f} (frozen fields {max(frozen):.4f}); "
         f"re-anchored {anchors} of {a.jumps * len(run_lats)} jumps; plain LBM {t_lbm * 1e3:.1f} ms, "
         f"surrogate {t_sur * 1e3:.1f} ms, speedup {t_lbm / t_sur:.2f}")
+    # the same network under other re-anchoring policies (same start, same reference)
+    report["policies"] = []
+    for pol in [x for x in a.policies.split(",") if x]:
+        dmax, chk = float(pol.split(":")[0]), int(pol.split(":")[1])
+        for lat, blob in zip(run_lats, blobs):
+            lat.load(blob)
+        torch.cuda.synchronize()
+        e0.record()
+        fin_p, anchors_p, _ = rollout(net, run_lats, test_inst, tcond, norm, a.t0, a.jumps, a.jump, dmax, chk, log)
+        e1.record()
+        torch.cuda.synchronize()
+        t_p = e0.elapsed_time(e1) / 1e3
+        err_p = rel_alpha(fin_p)
+        report["policies"].append({"defect_max": dmax, "check_every": chk, "rel_l2_alpha_max": max(err_p),
+                                   "rel_l2_alpha_mean": float(np.mean(err_p)), "anchors": anchors_p,
+                                   "seconds_surrogate": t_p, "speedup": t_lbm / t_p})
+        log(f"# policy defect_max {dmax:g}, check every {chk}: rel-L2 max {max(err_p):.4f} mean "
+            f"{np.mean(err_p):.4f}; re-anchored {anchors_p}; speedup {t_lbm / t_p:.2f}")
     if a.out:
         with open(a.out, "w") as fh:
             json.dump(report, fh, indent=1)
