@@ -30,12 +30,30 @@ def _lattices(ws, storage):
     return out
 
 
+def members_3d():
+    """Three uneven D3Q19 channels (walls on x and y, inlet z = 0)."""
+    out = []
+    for i, (nx, ny, nz) in enumerate([(70, 9, 12), (130, 6, 8), (40, 12, 10)]):
+        cfg = workloads._base("D3Q19", nx=nx, ny=ny, nz=nz, rho_l=100.0, drag="cgw", kappa_I=1e-3,
+                              g_hat=1e-6 / 99.0, up_axis=2, gamma=1.0, n_gamma=4,
+                              bc={"x-": "wall", "x+": "wall", "y-": "wall", "y+": "wall", "z-": "inlet",
+                                  "z+": "outlet"},
+                              alpha_in_max=0.1, alpha_in_min=0.01, ug_in_max=3e-3, ug_in_min=3e-4,
+                              ul_in_max=5e-4, ul_in_min=0.0, n_ramp=20.0)
+        f = workloads.smooth_random_3d(max(nx, ny, nz), seed=30 + i, alpha0=0.05, amp_a=0.02)
+        f = {k: np.ascontiguousarray(v[..., :nz, :ny, :nx]) for k, v in f.items()}
+        f["inlet_noise"] = 1.0 + 0.1 * np.random.default_rng(40 + i).uniform(-1, 1, (ny, nx))
+        out.append((cfg, f))
+    return out
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16", "fp64"])
 @pytest.mark.parametrize("graph_steps", [0, 8])
-def test_batch_equals_members_alone(graph_steps):
+def test_batch_equals_members_alone(graph_steps, storage):
     from paper_2409_10399_amd import Batch
     ws = members()
-    alone = _lattices(ws, "fp32")
-    batched = _lattices(ws, "fp32")
+    alone = _lattices(ws, storage)
+    batched = _lattices(ws, storage)
     batch = Batch(batched, tile=(64, 4), graph_steps=graph_steps)
     # several advances (graph replays, remainders), with reads in between
     for n in (8, 3, 16, 5):
@@ -50,6 +68,23 @@ def test_batch_equals_members_alone(graph_steps):
             da, db = a.diag(), b.diag()
             assert da["nonfinite"] == 0 and db["nonfinite"] == 0
             assert abs(da["alpha_g"] - db["alpha_g"]) < 1e-9
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_batch_equals_members_alone_d3q19(storage):
+    from paper_2409_10399_amd import Batch
+    ws = members_3d()
+    alone = _lattices(ws, storage)
+    batched = _lattices(ws, storage)
+    batch = Batch(batched, tile=(64, 2), graph_steps=6)
+    for n in (6, 5, 12):
+        batch.advance(n)
+        for lat in alone:
+            lat.set_launch(64, 2)
+            lat.advance(n)
+        for a, b in zip(alone, batched):
+            for k in FIELDS:
+                assert np.array_equal(a.read(k), b.read(k)), (storage, n, k)
 
 
 def test_batch_member_matches_oracle():
