@@ -455,9 +455,11 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
             // Interior wavefront (64 lanes = one x-block, see pop_in_plane): the
             // source of direction q lies in x-block xb of row y - c_y (plane
             // z - c_z), or in its neighbour block for the lane at the block
-            // edge.  The wave-uniform part, taken from block xb - 1, goes in
-            // the SGPR offset; the three per-lane parts (one per c_x) are
-            // computed once.
+            // edge.  The block part, taken from block xb - 1, is uniform
+            // across the wave, but it derives from the thread index, so the
+            // compiler cannot prove it: as an SGPR offset it would wrap each
+            // access in a loop over lane values.  It is added to one of the
+            // three per-lane parts (one per c_x, computed once) instead.
             const int xb = x >> 6, xl = x & 63;
             unsigned vo[3];
 #pragma unroll
@@ -474,21 +476,17 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                 const long long blk = (long long)(y - L::c[q][1]) * p.nxb + (xb - 1);
                 const unsigned so = (unsigned)((blk * kBlk + q * 256) * (long long)sizeof(T));
                 C g4[4];
-                Pop4<T>::ld(rp[L::c[q][2] + 1], vo[L::c[q][0] + 1], so, g4);
+                Pop4<T>::ld(rp[L::c[q][2] + 1], vo[L::c[q][0] + 1] + so, 0u, g4);
 #pragma unroll
                 for (int s = 0; s < 4; ++s) f[s][q] = g4[s];
             }
         } else {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const int xs = wrap_axis(x - L::c[q][0], p.nx, p.per[0]);
-                const int ys = wrap_axis(y - L::c[q][1], p.ny, p.per[1]);
-                const int zs = wrap_axis(z - L::c[q][2], p.nz, p.per[2]);
-                C g4[4];
-                Pop4<T>::ld(rsrc(pin + (long long)zs * p.plane), pop_in_plane<L>(p, xs, ys, q) * (unsigned)sizeof(T), 0, g4);
-#pragma unroll
-                for (int s = 0; s < 4; ++s) f[s][q] = g4[s];
-            }
+            // direction q of this lane arrives through a wall or the
+            // inlet/outlet plane (bit q of bmask): the boundary rules below
+            // start from the node's own post-collision population of the
+            // opposite direction, so the gather loads that one in place of
+            // the pull (one batch of Q loads, no second, dependent load)
+            unsigned bmask = 0u;
             if constexpr (CH) {
                 if (edge) {
 #pragma unroll
@@ -503,11 +501,36 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                             const int cfa = fa == 0 ? L::c[q][0] : (fa == 1 ? L::c[q][1] : L::c[q][2]);
                             flow = (fs == 0 && cfa == 1) || (fs == 1 && cfa == -1);
                         }
-                        if (!(wall || flow)) continue;
-                        const int qo = L::opp[q];
-                        C fo[4];
-                        Pop4<T>::ld(rsrc(pin + (long long)z * p.plane), pop_in_plane<L>(p, x, y, qo) * (unsigned)sizeof(T), 0,
-                                    fo);
+                        if (wall || flow) bmask |= 1u << q;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const bool bnd = (bmask >> q) & 1u;
+                const int xs = bnd ? x : wrap_axis(x - L::c[q][0], p.nx, p.per[0]);
+                const int ys = bnd ? y : wrap_axis(y - L::c[q][1], p.ny, p.per[1]);
+                const int zs = bnd ? z : wrap_axis(z - L::c[q][2], p.nz, p.per[2]);
+                C g4[4];
+                Pop4<T>::ld(rsrc(pin + (long long)zs * p.plane),
+                            pop_in_plane<L>(p, xs, ys, bnd ? L::opp[q] : q) * (unsigned)sizeof(T), 0, g4);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) f[s][q] = g4[s];
+            }
+            if constexpr (CH) {
+                if (edge) {
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        if (!((bmask >> q) & 1u)) continue;
+                        bool wall = false;
+#pragma unroll
+                        for (int a = 0; a < D; ++a) {
+                            wall = wall || (lo[a] && L::c[q][a] == 1 && p.wall_lo[a]) ||
+                                   (hi[a] && L::c[q][a] == -1 && p.wall_hi[a]);
+                        }
+                        C fo[4];  // the node's own population of the opposite direction
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) fo[s] = f[s][q];
                         const C wq = C(L::w[q]);
                         if (wall) {
                             // half-way bounce-back, zero wall velocity
@@ -788,8 +811,8 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
 
         // ---------------------------------------------------- collisions
         T* pout = static_cast<T*>(b.pop_out);
-        // the node's own block: plane descriptor, wave-uniform block offset,
-        // per-lane lane offset
+        // the node's own block: plane descriptor, plus the block offset
+        // (uniform across the wave) and the lane offset in the per-lane offset
         const __amdgpu_buffer_rsrc_t ro = rsrc(pout + (long long)z * p.plane);
         const long long oblk = ((long long)y * p.nxb + (x >> 6)) * kBlk;
         const unsigned vl = (unsigned)((x & 63) * 4 * (int)sizeof(T));
@@ -828,7 +851,7 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                 const C o2 = koa * f[2][q] + wq * (Aa + Ba * sg2);
                 const C o3 = kob * f[3][q] + wq * (Ab + Bb * sl2);
                 const C o4[4] = {o0, o1, o2, o3};
-                Pop4<T>::st(ro, vl, (unsigned)((oblk + q * 256) * (long long)sizeof(T)), o4);
+                Pop4<T>::st(ro, vl + (unsigned)((oblk + q * 256) * (long long)sizeof(T)), 0u, o4);
             }
         }
 
