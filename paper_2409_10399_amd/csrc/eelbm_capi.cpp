@@ -49,6 +49,7 @@ struct Geometry {
     int nblocks;
     int ntx, nty, xcd_remap;
     bool channel;
+    int bc_mode;  // kBc* configuration the step kernels are compiled for
 };
 
 int env_int(const char* name, int dflt) {
@@ -148,6 +149,9 @@ int validate(const eelbm_params* pp, Geometry* g) {
         set_tiles(p, g, 0, 0, -1);
         g->channel = false;
         for (int f = 0; f < 2 * D; ++f) g->channel = g->channel || p.bc[f] != EELBM_BC_PERIODIC;
+        bool column = p.bc[2 * (D - 1)] == EELBM_BC_INLET && p.bc[2 * (D - 1) + 1] == EELBM_BC_OUTLET;
+        for (int f = 0; f < 2 * (D - 1); ++f) column = column && p.bc[f] == EELBM_BC_WALL;
+        g->bc_mode = !g->channel ? kBcPeriodic : (column ? kBcColumn : kBcGeneric);
     }
     return EELBM_OK;
 }
@@ -308,7 +312,7 @@ int launch(eelbm_handle* h, bool init, int64_t t, bool last) {
     const int in = init ? 1 - (int)(t & 1) : h->cur;
     const int out = init ? (int)(t & 1) : 1 - h->cur;
     KBuffers b = buffers(h, in, out);
-    hipError_t e = launch_step(h->p.lattice, h->p.storage, h->g.channel, init, h->kp, b, c, h->g.grid, h->g.block,
+    hipError_t e = launch_step(h->p.lattice, h->p.storage, h->g.bc_mode, init, h->kp, b, c, h->g.grid, h->g.block,
                                h->stream);
     if (e != hipSuccess) return hip_fail(e, "k_step launch");
     if (last) h->diag_blocks = h->g.nblocks;
@@ -710,7 +714,7 @@ int eelbm_map_physical(double g, double kappa_I, double g_hat, double kappa_hat,
 struct eelbm_batch {
     std::vector<eelbm_handle*> m;
     int lattice, storage;
-    bool channel;
+    int bc_mode;  // kBc* configuration of the step kernel; members agree on it or it is kBcGeneric
     char* mem;
     size_t bytes;
     hipStream_t user;     // caller's stream: advance is ordered after its work and before later work
@@ -768,7 +772,7 @@ int batch_step_launches(eelbm_batch* b, int64_t nsteps, hipStream_t s) {
     const uint2* work = reinterpret_cast<const uint2*>(b->mem + b->off_work);
     long long* clock = reinterpret_cast<long long*>(b->mem + b->off_clock);
     for (int64_t k = 0; k < nsteps; ++k) {
-        hipError_t e = launch_batch_step(b->lattice, b->storage, b->channel, lat, work, b->nwork, clock, (int)k,
+        hipError_t e = launch_batch_step(b->lattice, b->storage, b->bc_mode, lat, work, b->nwork, clock, (int)k,
                                          k == nsteps - 1, b->block, s);
         if (e != hipSuccess) return hip_fail(e, "batch step launch");
     }
@@ -818,7 +822,9 @@ int eelbm_batch_create(eelbm_handle* const* members, int32_t n, int32_t tile_x, 
     b->m.assign(members, members + n);
     b->lattice = members[0]->p.lattice;
     b->storage = members[0]->p.storage;
-    b->channel = members[0]->g.channel;
+    b->bc_mode = members[0]->g.bc_mode;
+    for (int32_t i = 1; i < n; ++i)
+        if (members[i]->g.bc_mode != b->bc_mode) b->bc_mode = kBcGeneric;
     b->mem = static_cast<char*>(device_mem);
     b->bytes = bytes;
     b->user = static_cast<hipStream_t>(hip_stream);
@@ -932,7 +938,7 @@ int eelbm_autotune(eelbm_handle* h, int32_t steps, int32_t force, int32_t* tile_
     // key: lattice, storage, boundary kind, size class (floor log2 of the node count)
     int cls = 0;
     for (long long v = h->g.n; v > 1; v >>= 1) ++cls;
-    const long long key = (((long long)h->p.lattice * 8 + h->p.storage) * 2 + (h->g.channel ? 1 : 0)) * 64 + cls;
+    const long long key = (((long long)h->p.lattice * 8 + h->p.storage) * 3 + h->g.bc_mode) * 64 + cls;
     static std::mutex mu;
     static std::map<long long, std::array<int, 3>> cache;
     {

@@ -71,11 +71,19 @@ struct BatchLattice {
     KBuffers buf[2];
 };
 
-// storage: 0 FP64, 1 FP32, 2 FP16, 3 BF16; lattice: 2 D2Q9, 3 D3Q19
-hipError_t launch_step(int lattice, int storage, bool channel, bool init, const KParams& p,
+// boundary configuration a step is compiled for: every axis periodic; any
+// mix of periodic, wall and inlet/outlet faces read from KParams; the
+// standard column (inlet at the low and outlet at the high face of the last
+// axis, walls on every face of the other axes)
+constexpr int kBcPeriodic = 0;
+constexpr int kBcGeneric = 1;
+constexpr int kBcColumn = 2;
+
+// storage: 0 FP64, 1 FP32, 2 FP16, 3 BF16; lattice: 2 D2Q9, 3 D3Q19; bc: kBc*
+hipError_t launch_step(int lattice, int storage, int bc, bool init, const KParams& p,
                        const KBuffers& b, const KCtl& c, dim3 grid, dim3 block, hipStream_t s);
 // one step of every lattice of a batch: grid = work items (lattice, tile)
-hipError_t launch_batch_step(int lattice, int storage, bool channel, const BatchLattice* lat, const uint2* work,
+hipError_t launch_batch_step(int lattice, int storage, int bc, const BatchLattice* lat, const uint2* work,
                              long long nwork, const long long* clock, int k, int write_last, dim3 block,
                              hipStream_t s);
 hipError_t launch_clock_add(long long* clock, long long add, hipStream_t s);

@@ -288,13 +288,25 @@ __device__ __forceinline__ double ramp(double t, double ymax, double ymin, doubl
 // them); the steps that never write them run an instantiation without that
 // code, which needs fewer registers (D2Q9 FP32 channel: 88 instead of 99
 // VGPRs, 5 waves per SIMD instead of 4) and computes the same bits.
-template <class L, class T, bool CH, bool INIT, bool OUT = true>
+template <class L, class T, int BC, bool INIT, bool OUT = true>
 __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, const KCtl& ctl, long long tile,
                                           long long part) {
     using C = typename Compute<T>::C;
     constexpr int D = L::D;
     constexpr int Q = L::Q;
     constexpr int NPI = L::NPI;
+    // Boundary configuration: compile-time constants for a lattice periodic
+    // on every axis (BC = kBcPeriodic) and for the standard column (flow
+    // along the last axis, inlet at its low face, outlet at its high face,
+    // walls on every other face: BC = kBcColumn); the launch parameters for
+    // any other channel (kBcGeneric).  Constants keep the boundary code from
+    // holding scalar registers the rest of the step needs.
+    constexpr bool CH = BC != kBcPeriodic;
+    auto per = [&](int a) { return BC == kBcPeriodic ? 1 : (BC == kBcColumn ? int(a >= D) : p.per[a]); };
+    auto wall_lo = [&](int a) { return BC == kBcColumn ? int(a < D - 1) : p.wall_lo[a]; };
+    auto wall_hi = [&](int a) { return BC == kBcColumn ? int(a < D - 1) : p.wall_hi[a]; };
+    const int face_lo = BC == kBcColumn ? int(EELBM_BC_INLET) : p.face_lo;
+    const int face_hi = BC == kBcColumn ? int(EELBM_BC_OUTLET) : p.face_hi;
     constexpr int NV = 2 * D + 4;  // side-buffer values per node
     constexpr int kBlk = 4 * Q * 64;  // population elements of one x-block
     const C third = C(1) / C(3);
@@ -341,23 +353,23 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
         int fs = -1;            // flow-axis face this node lies on (0 low, 1 high)
         int ftype = EELBM_BC_PERIODIC;
         long long fidx = 0;     // node index within that face
-        const int fa = p.flow_axis;
+        const int fa = BC == kBcColumn ? D - 1 : p.flow_axis;
         if constexpr (CH) {
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                lo[a] = !p.per[a] && co[a] == 0;
-                hi[a] = !p.per[a] && co[a] == nn[a] - 1;
+                lo[a] = !per(a) && co[a] == 0;
+                hi[a] = !per(a) && co[a] == nn[a] - 1;
                 edge = edge || lo[a] || hi[a];
             }
             if (fa >= 0) {
                 fidx = fa == 0 ? (long long)z * p.ny + y : (fa == 1 ? (long long)z * p.nx + x : (long long)y * p.nx + x);
                 const int cf = co[fa];
-                if (cf == 0 && (p.face_lo == EELBM_BC_INLET || p.face_lo == EELBM_BC_OUTLET)) {
+                if (cf == 0 && (face_lo == EELBM_BC_INLET || face_lo == EELBM_BC_OUTLET)) {
                     fs = 0;
-                    ftype = p.face_lo;
-                } else if (cf == nn[fa] - 1 && (p.face_hi == EELBM_BC_INLET || p.face_hi == EELBM_BC_OUTLET)) {
+                    ftype = face_lo;
+                } else if (cf == nn[fa] - 1 && (face_hi == EELBM_BC_INLET || face_hi == EELBM_BC_OUTLET)) {
                     fs = 1;
-                    ftype = p.face_hi;
+                    ftype = face_hi;
                 }
             }
         }
@@ -494,8 +506,8 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                         bool wall = false, flow = false;
 #pragma unroll
                         for (int a = 0; a < D; ++a) {
-                            wall = wall || (lo[a] && L::c[q][a] == 1 && p.wall_lo[a]) ||
-                                   (hi[a] && L::c[q][a] == -1 && p.wall_hi[a]);
+                            wall = wall || (lo[a] && L::c[q][a] == 1 && wall_lo(a)) ||
+                                   (hi[a] && L::c[q][a] == -1 && wall_hi(a));
                         }
                         if (!wall && fs >= 0) {
                             const int cfa = fa == 0 ? L::c[q][0] : (fa == 1 ? L::c[q][1] : L::c[q][2]);
@@ -508,9 +520,9 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const bool bnd = (bmask >> q) & 1u;
-                const int xs = bnd ? x : wrap_axis(x - L::c[q][0], p.nx, p.per[0]);
-                const int ys = bnd ? y : wrap_axis(y - L::c[q][1], p.ny, p.per[1]);
-                const int zs = bnd ? z : wrap_axis(z - L::c[q][2], p.nz, p.per[2]);
+                const int xs = bnd ? x : wrap_axis(x - L::c[q][0], p.nx, per(0));
+                const int ys = bnd ? y : wrap_axis(y - L::c[q][1], p.ny, per(1));
+                const int zs = bnd ? z : wrap_axis(z - L::c[q][2], p.nz, per(2));
                 C g4[4];
                 Pop4<T>::ld(rsrc(pin + (long long)zs * p.plane),
                             pop_in_plane<L>(p, xs, ys, bnd ? L::opp[q] : q) * (unsigned)sizeof(T), 0, g4);
@@ -525,8 +537,8 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                         bool wall = false;
 #pragma unroll
                         for (int a = 0; a < D; ++a) {
-                            wall = wall || (lo[a] && L::c[q][a] == 1 && p.wall_lo[a]) ||
-                                   (hi[a] && L::c[q][a] == -1 && p.wall_hi[a]);
+                            wall = wall || (lo[a] && L::c[q][a] == 1 && wall_lo(a)) ||
+                                   (hi[a] && L::c[q][a] == -1 && wall_hi(a));
                         }
                         C fo[4];  // the node's own population of the opposite direction
 #pragma unroll
@@ -601,8 +613,8 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                     if (edge) {
 #pragma unroll
                         for (int a = 0; a < D; ++a) {
-                            wall = wall || (lo[a] && L::c[q][a] == 1 && p.wall_lo[a]) ||
-                                   (hi[a] && L::c[q][a] == -1 && p.wall_hi[a]);
+                            wall = wall || (lo[a] && L::c[q][a] == 1 && wall_lo(a)) ||
+                                   (hi[a] && L::c[q][a] == -1 && wall_hi(a));
                         }
                         if (!wall && fs >= 0) {
                             const int cfa = fa == 0 ? L::c[q][0] : (fa == 1 ? L::c[q][1] : L::c[q][2]);
@@ -622,9 +634,9 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                     dbg = wq * (dbgB + (C(1) + dbgB) * poly2(dotc<L>(q, cgB), usg));
                     dbl = wq * (dblB + (C(1) + dblB) * poly2(dotc<L>(q, clB), usl));
                 } else {
-                    const int xs = wrap_axis(x - L::c[q][0], p.nx, p.per[0]);
-                    const int ys = wrap_axis(y - L::c[q][1], p.ny, p.per[1]);
-                    const int zs = wrap_axis(z - L::c[q][2], p.nz, p.per[2]);
+                    const int xs = wrap_axis(x - L::c[q][0], p.nx, per(0));
+                    const int ys = wrap_axis(y - L::c[q][1], p.ny, per(1));
+                    const int zs = wrap_axis(z - L::c[q][2], p.nz, per(2));
                     const long long src = ((long long)zs * p.ny + ys) * p.nx + xs;
                     C as, als, du[D];
                     if constexpr (INIT) {
@@ -871,8 +883,8 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
             if (fa >= 0) {
                 const int cf = co[fa];
                 int side = -1, layer = 0;
-                const bool lo_open = p.face_lo == EELBM_BC_INLET || p.face_lo == EELBM_BC_OUTLET;
-                const bool hi_open = p.face_hi == EELBM_BC_INLET || p.face_hi == EELBM_BC_OUTLET;
+                const bool lo_open = face_lo == EELBM_BC_INLET || face_lo == EELBM_BC_OUTLET;
+                const bool hi_open = face_hi == EELBM_BC_INLET || face_hi == EELBM_BC_OUTLET;
                 if (lo_open && cf <= 1) {
                     side = 0;
                     layer = cf;
@@ -963,16 +975,16 @@ __device__ __forceinline__ long long xcd_tile(long long id, long long nb, int re
     return id < per * 8 ? (id & 7) * per + (id >> 3) : id;
 }
 
-template <class L, class T, bool CH, bool INIT, bool OUT>
+template <class L, class T, int BC, bool INIT, bool OUT>
 __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b, const KCtl ctl) {
-    step_body<L, T, CH, INIT, OUT>(p, b, ctl, xcd_tile(blockIdx.x, gridDim.x, p.xcd_remap), blockIdx.x);
+    step_body<L, T, BC, INIT, OUT>(p, b, ctl, xcd_tile(blockIdx.x, gridDim.x, p.xcd_remap), blockIdx.x);
 }
 
 // Batched step: one launch advances every lattice of a batch by one step.
 // Work item w = (lattice, tile); each lattice brings its own parameters and
 // both ping-pong buffer sets; the step's time is the batch clock + k + 1, so
 // a captured sequence of launches replays correctly at any time.
-template <class L, class T, bool CH, bool OUT>
+template <class L, class T, int BC, bool OUT>
 __global__ void __launch_bounds__(256) k_step_batch(const BatchLattice* lat, const uint2* work,
                                                     const long long* clock, int k, int write_last) {
     const uint2 w = work[xcd_tile(blockIdx.x, gridDim.x, 1)];
@@ -984,7 +996,7 @@ __global__ void __launch_bounds__(256) k_step_batch(const BatchLattice* lat, con
     c.write_macro = write_last;
     c.write_diag = write_last;
     const KBuffers bb = d.buf[(c.t - 1) & 1];
-    step_body<L, T, CH, false, OUT>(p, bb, c, w.y, w.y);
+    step_body<L, T, BC, false, OUT>(p, bb, c, w.y, w.y);
 }
 
 __global__ void k_clock_add(long long* clock, long long add) {
@@ -1035,83 +1047,96 @@ __global__ void __launch_bounds__(256) k_convert(const double* src, void* dst, i
 }
 
 // ------------------------------------------------------------ launchers
-template <class L, class T, bool CH, bool INIT, bool OUT>
+template <class L, class T, int BC, bool INIT, bool OUT>
 static hipError_t go(const KParams& p, const KBuffers& b, const KCtl& c, dim3 g, dim3 bl, hipStream_t s) {
-    hipLaunchKernelGGL((k_step<L, T, CH, INIT, OUT>), g, bl, 0, s, p, b, c);
+    hipLaunchKernelGGL((k_step<L, T, BC, INIT, OUT>), g, bl, 0, s, p, b, c);
     return hipGetLastError();
 }
 
-// the initial step always writes the read-out; a later step takes the
-// instantiation without it unless its control asks for diagnostics or fields
-template <class L, class T, bool CH>
+// the initial step always writes the read-out (the standard column's uses the
+// generic channel instantiation); a later step takes the instantiation
+// without read-out unless its control asks for diagnostics or fields
+template <class L, class T, int BC>
 static hipError_t go3(bool init, const KParams& p, const KBuffers& b, const KCtl& c, dim3 g, dim3 bl,
                       hipStream_t s) {
-    if (init) return go<L, T, CH, true, true>(p, b, c, g, bl, s);
-    if (c.write_diag || c.write_macro) return go<L, T, CH, false, true>(p, b, c, g, bl, s);
-    return go<L, T, CH, false, false>(p, b, c, g, bl, s);
+    if (init) return go<L, T, BC == kBcColumn ? kBcGeneric : BC, true, true>(p, b, c, g, bl, s);
+    if (c.write_diag || c.write_macro) return go<L, T, BC, false, true>(p, b, c, g, bl, s);
+    return go<L, T, BC, false, false>(p, b, c, g, bl, s);
 }
 
 template <class L, class T>
-static hipError_t go2(bool ch, bool init, const KParams& p, const KBuffers& b, const KCtl& c, dim3 g, dim3 bl,
+static hipError_t go2(int bc, bool init, const KParams& p, const KBuffers& b, const KCtl& c, dim3 g, dim3 bl,
                       hipStream_t s) {
-    return ch ? go3<L, T, true>(init, p, b, c, g, bl, s) : go3<L, T, false>(init, p, b, c, g, bl, s);
-}
-
-template <class L>
-static hipError_t go1(int storage, bool ch, bool init, const KParams& p, const KBuffers& b, const KCtl& c, dim3 g,
-                      dim3 bl, hipStream_t s) {
-    switch (storage) {
-        case EELBM_FP64: return go2<L, double>(ch, init, p, b, c, g, bl, s);
-        case EELBM_FP32: return go2<L, float>(ch, init, p, b, c, g, bl, s);
-        case EELBM_FP16: return go2<L, __half>(ch, init, p, b, c, g, bl, s);
-        case EELBM_BF16: return go2<L, __hip_bfloat16>(ch, init, p, b, c, g, bl, s);
+    switch (bc) {
+        case kBcPeriodic: return go3<L, T, kBcPeriodic>(init, p, b, c, g, bl, s);
+        case kBcGeneric: return go3<L, T, kBcGeneric>(init, p, b, c, g, bl, s);
+        case kBcColumn: return go3<L, T, kBcColumn>(init, p, b, c, g, bl, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_step(int lattice, int storage, bool channel, bool init, const KParams& p, const KBuffers& b,
+template <class L>
+static hipError_t go1(int storage, int bc, bool init, const KParams& p, const KBuffers& b, const KCtl& c, dim3 g,
+                      dim3 bl, hipStream_t s) {
+    switch (storage) {
+        case EELBM_FP64: return go2<L, double>(bc, init, p, b, c, g, bl, s);
+        case EELBM_FP32: return go2<L, float>(bc, init, p, b, c, g, bl, s);
+        case EELBM_FP16: return go2<L, __half>(bc, init, p, b, c, g, bl, s);
+        case EELBM_BF16: return go2<L, __hip_bfloat16>(bc, init, p, b, c, g, bl, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_step(int lattice, int storage, int bc, bool init, const KParams& p, const KBuffers& b,
                        const KCtl& c, dim3 grid, dim3 block, hipStream_t s) {
-    if (lattice == EELBM_D2Q9) return go1<D2Q9>(storage, channel, init, p, b, c, grid, block, s);
-    if (lattice == EELBM_D3Q19) return go1<D3Q19>(storage, channel, init, p, b, c, grid, block, s);
+    if (lattice == EELBM_D2Q9) return go1<D2Q9>(storage, bc, init, p, b, c, grid, block, s);
+    if (lattice == EELBM_D3Q19) return go1<D3Q19>(storage, bc, init, p, b, c, grid, block, s);
     return hipErrorInvalidValue;
 }
 
 template <class L, class T, bool OUT>
-static hipError_t gob_out(bool ch, const BatchLattice* lat, const uint2* work, long long nwork,
+static hipError_t gob_out(int bc, const BatchLattice* lat, const uint2* work, long long nwork,
                           const long long* clock, int k, int write_last, dim3 block, hipStream_t s) {
-    if (ch)
-        hipLaunchKernelGGL((k_step_batch<L, T, true, OUT>), dim3((unsigned)nwork), block, 0, s, lat, work, clock, k,
-                           write_last);
-    else
-        hipLaunchKernelGGL((k_step_batch<L, T, false, OUT>), dim3((unsigned)nwork), block, 0, s, lat, work, clock,
-                           k, write_last);
+    const dim3 g((unsigned)nwork);
+    switch (bc) {
+        case kBcPeriodic:
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcPeriodic, OUT>), g, block, 0, s, lat, work, clock, k, write_last);
+            break;
+        case kBcGeneric:
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcGeneric, OUT>), g, block, 0, s, lat, work, clock, k, write_last);
+            break;
+        case kBcColumn:
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcColumn, OUT>), g, block, 0, s, lat, work, clock, k, write_last);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 template <class L, class T>
-static hipError_t gob(bool ch, const BatchLattice* lat, const uint2* work, long long nwork, const long long* clock,
+static hipError_t gob(int bc, const BatchLattice* lat, const uint2* work, long long nwork, const long long* clock,
                       int k, int write_last, dim3 block, hipStream_t s) {
-    return write_last ? gob_out<L, T, true>(ch, lat, work, nwork, clock, k, write_last, block, s)
-                      : gob_out<L, T, false>(ch, lat, work, nwork, clock, k, write_last, block, s);
+    return write_last ? gob_out<L, T, true>(bc, lat, work, nwork, clock, k, write_last, block, s)
+                      : gob_out<L, T, false>(bc, lat, work, nwork, clock, k, write_last, block, s);
 }
 
 template <class L>
-static hipError_t gob1(int storage, bool ch, const BatchLattice* lat, const uint2* work, long long nwork,
+static hipError_t gob1(int storage, int bc, const BatchLattice* lat, const uint2* work, long long nwork,
                        const long long* clock, int k, int write_last, dim3 block, hipStream_t s) {
     switch (storage) {
-        case EELBM_FP64: return gob<L, double>(ch, lat, work, nwork, clock, k, write_last, block, s);
-        case EELBM_FP32: return gob<L, float>(ch, lat, work, nwork, clock, k, write_last, block, s);
-        case EELBM_FP16: return gob<L, __half>(ch, lat, work, nwork, clock, k, write_last, block, s);
-        case EELBM_BF16: return gob<L, __hip_bfloat16>(ch, lat, work, nwork, clock, k, write_last, block, s);
+        case EELBM_FP64: return gob<L, double>(bc, lat, work, nwork, clock, k, write_last, block, s);
+        case EELBM_FP32: return gob<L, float>(bc, lat, work, nwork, clock, k, write_last, block, s);
+        case EELBM_FP16: return gob<L, __half>(bc, lat, work, nwork, clock, k, write_last, block, s);
+        case EELBM_BF16: return gob<L, __hip_bfloat16>(bc, lat, work, nwork, clock, k, write_last, block, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_step(int lattice, int storage, bool channel, const BatchLattice* lat, const uint2* work,
+hipError_t launch_batch_step(int lattice, int storage, int bc, const BatchLattice* lat, const uint2* work,
                              long long nwork, const long long* clock, int k, int write_last, dim3 block,
                              hipStream_t s) {
-    if (lattice == EELBM_D2Q9) return gob1<D2Q9>(storage, channel, lat, work, nwork, clock, k, write_last, block, s);
-    if (lattice == EELBM_D3Q19) return gob1<D3Q19>(storage, channel, lat, work, nwork, clock, k, write_last, block, s);
+    if (lattice == EELBM_D2Q9) return gob1<D2Q9>(storage, bc, lat, work, nwork, clock, k, write_last, block, s);
+    if (lattice == EELBM_D3Q19) return gob1<D3Q19>(storage, bc, lat, work, nwork, clock, k, write_last, block, s);
     return hipErrorInvalidValue;
 }
 
