@@ -522,7 +522,9 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                 const bool bnd = (bmask >> q) & 1u;
                 const int xs = bnd ? x : wrap_axis(x - L::c[q][0], p.nx, per(0));
                 const int ys = bnd ? y : wrap_axis(y - L::c[q][1], p.ny, per(1));
-                const int zs = bnd ? z : wrap_axis(z - L::c[q][2], p.nz, per(2));
+                // a pull within the node's own plane keeps the wavefront's plane
+                // (uniform across the wave, so the descriptor stays scalar)
+                const int zs = L::c[q][2] == 0 ? z : (bnd ? z : wrap_axis(z - L::c[q][2], p.nz, per(2)));
                 C g4[4];
                 Pop4<T>::ld(rsrc(pin + (long long)zs * p.plane),
                             pop_in_plane<L>(p, xs, ys, bnd ? L::opp[q] : q) * (unsigned)sizeof(T), 0, g4);
