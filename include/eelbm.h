@@ -290,7 +290,9 @@ int eelbm_autotune(eelbm_handle* h, int32_t steps, int32_t force, int32_t* tile_
  * on the matrix cores in BF16 with FP32 accumulation. */
 
 /* out = act(conv3x3(in; Wf) + bias), zero padding; act = leaky-ReLU with
- * `slope` if act != 0; bias may be NULL. */
+ * `slope` if act != 0; bias may be NULL.  One image (H * W * Cin) and the
+ * weight copy (9 * Cin * Cout) must each hold fewer than 2^31 values
+ * (EELBM_E_PARAM otherwise). */
 int eelbm_cno_conv_fwd(const float* in, int32_t B, int32_t H, int32_t W, int32_t Cin, const uint16_t* wf,
                        const float* bias, int32_t Cout, float* out, int32_t act, float slope, void* stream);
 /* din = gradient of the convolution wrt its input, given dout (the gradient

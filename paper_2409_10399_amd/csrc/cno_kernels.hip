@@ -34,13 +34,11 @@ __device__ __forceinline__ unsigned short bf16_bits(float f) {
 }
 __device__ __forceinline__ float bf16_float(unsigned short h) { return __builtin_bit_cast(float, (unsigned)h << 16); }
 
+// four FP32 values to BF16 (round to nearest even) with the packed hardware
+// conversion of gfx950
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ s16x4 pack4(const f32x4& v) {
-    s16x4 r;
-    r.x = (short)bf16_bits(v.x);
-    r.y = (short)bf16_bits(v.y);
-    r.z = (short)bf16_bits(v.z);
-    r.w = (short)bf16_bits(v.w);
-    return r;
+    return __builtin_bit_cast(s16x4, __builtin_convertvector(v, bf16x4));
 }
 
 __device__ __forceinline__ f32x4 mfma(const s16x4& a, const s16x4& b, const f32x4& c) {
@@ -52,54 +50,90 @@ constexpr int kMaxNT = 12;  // output-channel tiles of 16 one wavefront accumula
 // --------------------------------------------------------------- forward
 // out[b, y, x, co] = bias[co] + sum_{tap, ci} in[b, y + dy, x + dx, ci] Wf[co][tap][ci]
 // (zero padding), then leaky-ReLU with slope `slope` if act != 0.
-// Grid: x = pixel groups of 16 (rows padded), y = groups of NT output tiles.
-template <int NT>
+// A wavefront owns MT x 16 consecutive pixels of one image row (MT M-tiles)
+// and NT output tiles of 16 channels: each loaded weight fragment feeds MT
+// matrix-core products and each loaded pixel fragment NT.
+// Grid: x = pixel groups of 16 MT (rows padded), y = groups of NT output tiles.
+template <int MT, int NT>
 __global__ void __launch_bounds__(64) k_conv_fwd(const float* __restrict__ in, int B, int H, int W, int Cin,
                                                 const unsigned short* __restrict__ wf, const float* __restrict__ bias,
                                                 int Cout, float* __restrict__ out, int act, float slope) {
     const int lane = threadIdx.x;
-    const int gw = (W + 15) / 16;
+    const int gw = (W + 16 * MT - 1) / (16 * MT);
     const long long grp = blockIdx.x;
     const int xg = (int)(grp % gw);
     const long long by = grp / gw;  // b * H + y
     const int y = (int)(by % H);
     const int b = (int)(by / H);
-    const int x = xg * 16 + (lane & 15);  // pixel of this lane's A row
-    const int kq = 4 * (lane >> 4);       // K offset of this lane within a 16-chunk
-    const int n0 = blockIdx.y * NT * 16;
-    f32x4 acc[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int x0 = xg * 16 * MT + (lane & 15);  // pixel of this lane's A row in M-tile 0
+    const int kq = 4 * (lane >> 4);              // K offset of this lane within a 16-chunk
+    const int n0 = blockIdx.y * NT * 16;        // the host launches Cout / (16 NT) tiles exactly
     const int K = 9 * Cin;
-    for (int tap = 0; tap < 9; ++tap) {
-        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-        const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
-        const float* src = in + (((long long)b * H + (ok ? yy : 0)) * W + (ok ? xx : 0)) * Cin;
-        for (int c0 = 0; c0 < Cin; c0 += 16) {
-            f32x4 av = ok ? *reinterpret_cast<const f32x4*>(src + c0 + kq) : f32x4{0.f, 0.f, 0.f, 0.f};
-            const s16x4 a = pack4(av);
-            const int k = tap * Cin + c0 + kq;
+    const int nc = Cin / 16;  // 16-channel chunks per tap
+    f32x4 acc[MT][NT];
+    float bc[NT];
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const int co = n0 + j * 16 + (lane & 15);
-                const u16x4 wv = co < Cout ? *reinterpret_cast<const u16x4*>(wf + (long long)co * K + k)
-                                           : u16x4{0, 0, 0, 0};
-                acc[j] = mfma(a, __builtin_bit_cast(s16x4, wv), acc[j]);
-            }
+    for (int j = 0; j < NT; ++j) {
+        bc[j] = bias ? bias[n0 + j * 16 + (lane & 15)] : 0.f;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    const unsigned short* wrow = wf + (long long)(n0 + (lane & 15)) * K + kq;
+    const float* img = in + (long long)b * H * W * Cin + kq;  // H * W * Cin < 2^31 (host check)
+    // fragments of one (tap, chunk) step: loads always address a valid pixel
+    // (the image's first one when the tap falls outside), the value is
+    // zeroed after the load; the next step's loads are issued before this
+    // step's products
+    f32x4 av[MT];
+    u16x4 bv[NT];
+    bool ok[MT];
+    auto load = [&](int tap, int c0) {
+        const int yy = y + tap / 3 - 1;
+        const bool oky = (unsigned)yy < (unsigned)H;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int xx = x0 + 16 * m + tap % 3 - 1;
+            ok[m] = oky & ((unsigned)xx < (unsigned)W);
+            const int pix = ok[m] ? yy * W + xx : 0;
+            av[m] = *reinterpret_cast<const f32x4*>(img + (pix * Cin + c0));
         }
+        const int k = tap * Cin + c0;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) bv[j] = *reinterpret_cast<const u16x4*>(wrow + (j * 16 * K + k));
+    };
+    int tap = 0, ch = 0;
+    load(0, 0);
+    for (int it = 0; it < 9 * nc; ++it) {
+        s16x4 a[MT], bw[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const s16x4 h = pack4(av[m]);
+            a[m] = ok[m] ? h : s16x4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) bw[j] = __builtin_bit_cast(s16x4, bv[j]);
+        if (++ch == nc) {
+            ch = 0;
+            ++tap;
+        }
+        if (tap < 9) load(tap, ch * 16);
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[m][j] = mfma(a[m], bw[j], acc[m][j]);
     }
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const int co = n0 + j * 16 + (lane & 15);
-        if (co >= Cout) continue;
-        const float bc = bias ? bias[co] : 0.f;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int px = xg * 16 + 4 * (lane >> 4) + t;
-            if (px >= W) continue;
-            float v = acc[j][t] + bc;
-            if (act) v = v > 0.f ? v : slope * v;
-            out[(((long long)b * H + y) * W + px) * Cout + co] = v;
+        for (int m = 0; m < MT; ++m) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int px = xg * 16 * MT + 16 * m + 4 * (lane >> 4) + t;
+                float v = acc[m][j][t] + bc[j];
+                v = (act && v < 0.f) ? slope * v : v;
+                if (px < W) out[(((long long)b * H + y) * W + px) * Cout + co] = v;
+            }
         }
     }
 }
@@ -419,10 +453,27 @@ void tiles(int Cout, int* nt, int* gy) {
     *gy = tiles16 / best;
 }
 
-template <int NT>
-void fwd_nt(const float* in, int B, int H, int W, int Cin, const unsigned short* wf, const float* bias, int Cout,
-            float* out, int act, float slope, dim3 g, hipStream_t s) {
-    hipLaunchKernelGGL((k_conv_fwd<NT>), g, dim3(64), 0, s, in, B, H, W, Cin, wf, bias, Cout, out, act, slope);
+// forward tiling: MT M-tiles of 16 pixels (up to 4, no more than a row holds)
+// and NT <= 4 output tiles per wavefront, NT dividing the output tiles
+constexpr int kFwdMaxNT = 4;
+
+template <int MT, int NT>
+void fwd_mn(const float* in, int B, int H, int W, int Cin, const unsigned short* wf, const float* bias, int Cout,
+            float* out, int act, float slope, hipStream_t s) {
+    const dim3 g((unsigned)((long long)B * H * ((W + 16 * MT - 1) / (16 * MT))), (unsigned)(Cout / (16 * NT)));
+    hipLaunchKernelGGL((k_conv_fwd<MT, NT>), g, dim3(64), 0, s, in, B, H, W, Cin, wf, bias, Cout, out, act, slope);
+}
+
+template <int MT>
+bool fwd_m(int nt, const float* in, int B, int H, int W, int Cin, const unsigned short* wf, const float* bias,
+           int Cout, float* out, int act, float slope, hipStream_t s) {
+    switch (nt) {
+        case 1: fwd_mn<MT, 1>(in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s); return true;
+        case 2: fwd_mn<MT, 2>(in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s); return true;
+        case 3: fwd_mn<MT, 3>(in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s); return true;
+        case 4: fwd_mn<MT, 4>(in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s); return true;
+    }
+    return false;
 }
 template <int NT>
 void bwd_nt(const float* dout, int B, int H, int W, int Cout, const unsigned short* wd, int Cin, float* din, dim3 g,
@@ -441,17 +492,17 @@ extern "C" {
 int eelbm_cno_conv_fwd(const float* in, int32_t B, int32_t H, int32_t W, int32_t Cin, const uint16_t* wf,
                        const float* bias, int32_t Cout, float* out, int32_t act, float slope, void* stream) {
     if (!in || !wf || !out || !shape_ok(B, H, W, Cin, Cout)) return EELBM_E_PARAM;
-    int nt, gy;
-    tiles(Cout, &nt, &gy);
-    const dim3 g((unsigned)((long long)B * H * ((W + 15) / 16)), (unsigned)gy);
+    int nt = 1;
+    for (int d = 1; d <= kFwdMaxNT; ++d)
+        if ((Cout / 16) % d == 0) nt = d;
+    if ((long long)B * H * ((W + 15) / 16) >= (1ll << 32) || (long long)H * W * Cin >= (1ll << 31) ||
+        (long long)Cout * 9 * Cin >= (1ll << 31))
+        return EELBM_E_PARAM;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    switch (nt) {
-#define CASE(N) \
-    case N: fwd_nt<N>(in, B, H, W, Cin, wf, bias, Cout, out, act, slope, g, s); break;
-        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12)
-#undef CASE
-        default: return EELBM_E_PARAM;
-    }
+    const bool ok = W >= 64   ? fwd_m<4>(nt, in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s)
+                    : W >= 32 ? fwd_m<2>(nt, in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s)
+                              : fwd_m<1>(nt, in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s);
+    if (!ok) return EELBM_E_PARAM;
     return last_rc(hipGetLastError());
 }
 

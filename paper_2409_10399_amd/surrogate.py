@@ -259,3 +259,37 @@ def apply_output(fields, net_out, dscale):
     _check(lib().eelbm_cno_unpack(_p(fields), _p(net_out), H * W, nf, net_out.shape[3], _p(dscale), B, _p(out),
                                   _stream()))
     return out
+
+
+def _time_forward():
+    """Time the forward pass of a randomly initialised network on a random
+    NHWC input with HIP events: python -m paper_2409_10399_amd.surrogate
+    [--widths 32,48,96,192] [--batch 8] [--grid 256] [--reps 20]."""
+    import argparse
+    import json
+
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--widths", default="32,48,96,192")
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--reps", type=int, default=20)
+    a = ap.parse_args()
+    net = CNO(9, 6, [int(w) for w in a.widths.split(",")], seed=0)
+    x = torch.randn(a.batch, a.grid, a.grid, net.cin, device="cuda")
+    for _ in range(3):
+        net.forward(x)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(a.reps):
+        net.forward(x)
+    e1.record(st)
+    torch.cuda.synchronize()
+    print(json.dumps({"widths": net.widths, "params": net.n_params, "batch": a.batch, "grid": a.grid,
+                      "ms_per_forward": e0.elapsed_time(e1) / a.reps}), flush=True)
+
+
+if __name__ == "__main__":
+    _time_forward()

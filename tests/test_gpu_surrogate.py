@@ -33,7 +33,8 @@ def host(t):
     return t.double().cpu().numpy()
 
 
-@pytest.mark.parametrize("shape", [(2, 16, 32, 32, 48), (1, 8, 20, 16, 192), (3, 4, 16, 64, 16)])
+@pytest.mark.parametrize("shape", [(2, 16, 32, 32, 48), (1, 8, 20, 16, 192), (3, 4, 16, 64, 16), (1, 6, 72, 32, 96),
+                                   (2, 3, 128, 16, 64)])
 def test_conv_kernels_match_reference(shape):
     import torch
     from paper_2409_10399_amd.binding import lib
