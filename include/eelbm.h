@@ -286,8 +286,9 @@ int eelbm_autotune(eelbm_handle* h, int32_t steps, int32_t force, int32_t* tile_
  *
  * Convolution weights: FP32 master W[tap][ci][co] (tap = 3 (dy + 1) + dx + 1),
  * and two BF16 copies made by eelbm_cno_pack_weights: Wf[co][tap][ci] for the
- * forward pass and Wd[ci][tap][co] for the input gradient.  The products run
- * on the matrix cores in BF16 with FP32 accumulation. */
+ * forward pass and Wd[ci][8 - tap][co] (taps reversed) for the input
+ * gradient, which is then a forward convolution of dout with Wd.  The
+ * products run on the matrix cores in BF16 with FP32 accumulation. */
 
 /* out = act(conv3x3(in; Wf) + bias), zero padding; act = leaky-ReLU with
  * `slope` if act != 0; bias may be NULL.  One image (H * W * Cin) and the
@@ -296,12 +297,13 @@ int eelbm_autotune(eelbm_handle* h, int32_t steps, int32_t force, int32_t* tile_
 int eelbm_cno_conv_fwd(const float* in, int32_t B, int32_t H, int32_t W, int32_t Cin, const uint16_t* wf,
                        const float* bias, int32_t Cout, float* out, int32_t act, float slope, void* stream);
 /* din = gradient of the convolution wrt its input, given dout (the gradient
- * wrt the pre-activation output). */
+ * wrt the pre-activation output); the size limits of eelbm_cno_conv_fwd apply
+ * with the roles of Cin and Cout exchanged. */
 int eelbm_cno_conv_bwd_data(const float* dout, int32_t B, int32_t H, int32_t W, int32_t Cout, const uint16_t* wd,
                             int32_t Cin, float* din, void* stream);
 /* dw[tap][ci][co] += sum over pixels of in(shifted) * dout; dbias[co] += sum
  * of dout (dbias may be NULL).  Accumulates: zero them first (eelbm_cno_fill).
- * Cout <= 256. */
+ * Cout <= 256; B * H * W below 2^31 - 2048 pixels (EELBM_E_PARAM otherwise). */
 int eelbm_cno_conv_bwd_weight(const float* in, const float* dout, int32_t B, int32_t H, int32_t W, int32_t Cin,
                               int32_t Cout, float* dw, float* dbias, void* stream);
 /* dx = dy where y > 0, slope * dy elsewhere (y: the leaky-ReLU output). */

@@ -13,7 +13,7 @@
 //   A[m = l % 16][k = 4 (l / 16) + t],  B[k = 4 (l / 16) + t][n = l % 16],
 //   D[m = 4 (l / 16) + t][n = l % 16].
 // Weights: master FP32 W[tap][ci][co]; the forward pass reads the BF16 copy
-// Wf[co][tap][ci] and the input-gradient pass the BF16 copy Wd[ci][tap][co],
+// Wf[co][tap][ci] and the input-gradient pass the BF16 copy Wd[ci][8 - tap][co],
 // so that the four K-consecutive values a lane needs are adjacent.
 #include <hip/hip_runtime.h>
 
@@ -45,7 +45,6 @@ __device__ __forceinline__ f32x4 mfma(const s16x4& a, const s16x4& b, const f32x
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-constexpr int kMaxNT = 12;  // output-channel tiles of 16 one wavefront accumulates (192 channels)
 
 // --------------------------------------------------------------- forward
 // out[b, y, x, co] = bias[co] + sum_{tap, ci} in[b, y + dy, x + dx, ci] Wf[co][tap][ci]
@@ -139,54 +138,10 @@ __global__ void __launch_bounds__(64) k_conv_fwd(const float* __restrict__ in, i
 }
 
 // ----------------------------------------------------- gradient wrt input
-// din[b, y, x, ci] = sum_{tap, co} dout[b, y - dy, x - dx, co] Wd[ci][tap][co]
-template <int NT>
-__global__ void __launch_bounds__(64) k_conv_bwd_data(const float* __restrict__ dout, int B, int H, int W, int Cout,
-                                                     const unsigned short* __restrict__ wd, int Cin,
-                                                     float* __restrict__ din) {
-    const int lane = threadIdx.x;
-    const int gw = (W + 15) / 16;
-    const long long grp = blockIdx.x;
-    const int xg = (int)(grp % gw);
-    const long long by = grp / gw;
-    const int y = (int)(by % H);
-    const int b = (int)(by / H);
-    const int x = xg * 16 + (lane & 15);
-    const int kq = 4 * (lane >> 4);
-    const int n0 = blockIdx.y * NT * 16;
-    f32x4 acc[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int K = 9 * Cout;
-    for (int tap = 0; tap < 9; ++tap) {
-        const int yy = y - (tap / 3 - 1), xx = x - (tap % 3 - 1);
-        const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
-        const float* src = dout + (((long long)b * H + (ok ? yy : 0)) * W + (ok ? xx : 0)) * Cout;
-        for (int c0 = 0; c0 < Cout; c0 += 16) {
-            f32x4 av = ok ? *reinterpret_cast<const f32x4*>(src + c0 + kq) : f32x4{0.f, 0.f, 0.f, 0.f};
-            const s16x4 a = pack4(av);
-            const int k = tap * Cout + c0 + kq;
-#pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const int ci = n0 + j * 16 + (lane & 15);
-                const u16x4 wv = ci < Cin ? *reinterpret_cast<const u16x4*>(wd + (long long)ci * K + k)
-                                          : u16x4{0, 0, 0, 0};
-                acc[j] = mfma(a, __builtin_bit_cast(s16x4, wv), acc[j]);
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const int ci = n0 + j * 16 + (lane & 15);
-        if (ci >= Cin) continue;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int px = xg * 16 + 4 * (lane >> 4) + t;
-            if (px >= W) continue;
-            din[(((long long)b * H + y) * W + px) * Cin + ci] = acc[j][t];
-        }
-    }
-}
+// din[b, y, x, ci] = sum_{tap, co} dout[b, y - dy, x - dx, co] W[tap][ci][co]
+//                  = sum_{tap', co} dout[b, y + dy', x + dx', co] Wd[ci][tap'][co]
+// with the taps reversed (tap' = 8 - tap, dy' = -dy, dx' = -dx): a forward
+// convolution of dout with Wd, run by k_conv_fwd.
 
 // ---------------------------------------------------- gradient wrt weights
 // dW[tap][ci][co] += sum_p in[p + d_tap][ci] dout[p][co] over this
@@ -198,32 +153,47 @@ __global__ void __launch_bounds__(64) k_conv_bwd_weight(const float* __restrict_
     const int lane = threadIdx.x;
     const int mt = blockIdx.x;  // M tile over 9 * Cin
     const int nt = blockIdx.y;  // N tile over Cout
-    const long long P = (long long)B * H * W;
-    const long long p0 = (long long)blockIdx.z * chunk;
+    const int P = B * H * W;    // < 2^31 (host check)
+    const int p0 = blockIdx.z * chunk;
     const int m = mt * 16 + (lane & 15);
     const int tap = m / Cin, ci = m - tap * Cin;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
     const int co = nt * 16 + (lane & 15);
     const int kq = 4 * (lane >> 4);
+    // image coordinates of this lane's four pixels p = pk + kq + t, advanced
+    // by 16 pixels per step (no division in the loop)
+    int px[4], py[4], pb[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int p = p0 + kq + t;
+        px[t] = p % W;
+        const int r = p / W;
+        py[t] = r % H;
+        pb[t] = r / H;
+    }
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (long long pk = p0; pk < p0 + chunk && pk < P; pk += 16) {
+    const int pend = min(p0 + chunk, P);
+    for (int pk = p0; pk < pend; pk += 16) {
         f32x4 av, bv;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const long long p = pk + kq + t;
-            float a = 0.f, bb = 0.f;
-            if (p < P) {
-                const int px = (int)(p % W);
-                const long long r = p / W;
-                const int py = (int)(r % H);
-                const int pb = (int)(r / H);
-                const int yy = py + dy, xx = px + dx;
-                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    a = in[(((long long)pb * H + yy) * W + xx) * Cin + ci];
-                bb = dout[p * Cout + co];
+            const int p = pk + kq + t;
+            const int yy = py[t] + dy, xx = px[t] + dx;
+            const bool okp = p < pend;
+            const bool ok = okp && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W;
+            const long long src = ok ? ((long long)pb[t] * H + yy) * W + xx : 0;
+            const float a = in[src * Cin + ci];
+            const float bb = dout[(long long)(okp ? p : 0) * Cout + co];
+            av[t] = ok ? a : 0.f;
+            bv[t] = okp ? bb : 0.f;
+            px[t] += 16;
+            while (px[t] >= W) {
+                px[t] -= W;
+                if (++py[t] == H) {
+                    py[t] = 0;
+                    ++pb[t];
+                }
             }
-            av[t] = a;
-            bv[t] = bb;
         }
         acc = mfma(pack4(av), pack4(bv), acc);
     }
@@ -234,7 +204,6 @@ __global__ void __launch_bounds__(64) k_conv_bwd_weight(const float* __restrict_
     }
 }
 
-// ------------------------------------------------------------ elementwise
 __global__ void k_bias_grad(const float* __restrict__ dout, long long P, int C, float* __restrict__ db) {
     // one workgroup per 256-pixel chunk, one thread per channel (C <= 256)
     const int c = threadIdx.x;
@@ -381,7 +350,7 @@ __global__ void k_pack_weights(const float* __restrict__ w, int Cin, int Cout, u
         const int tap = (int)(r / Cin);
         const unsigned short h = bf16_bits(w[i]);
         wf[((long long)co * 9 + tap) * Cin + ci] = h;
-        wd[((long long)ci * 9 + tap) * Cout + co] = h;
+        wd[((long long)ci * 9 + (8 - tap)) * Cout + co] = h;
     }
 }
 
@@ -442,17 +411,6 @@ using namespace cno;
 namespace {
 int last_rc(hipError_t e) { return e == hipSuccess ? EELBM_OK : EELBM_E_HIP; }
 
-// pick the number of 16-wide output tiles per wavefront (<= kMaxNT) and the
-// grid's y extent
-void tiles(int Cout, int* nt, int* gy) {
-    const int tiles16 = Cout / 16;
-    int best = 1;
-    for (int d = 1; d <= kMaxNT; ++d)
-        if (tiles16 % d == 0) best = d;
-    *nt = best;
-    *gy = tiles16 / best;
-}
-
 // forward tiling: MT M-tiles of 16 pixels (up to 4, no more than a row holds)
 // and NT <= 4 output tiles per wavefront, NT dividing the output tiles
 constexpr int kFwdMaxNT = 4;
@@ -474,11 +432,6 @@ bool fwd_m(int nt, const float* in, int B, int H, int W, int Cin, const unsigned
         case 4: fwd_mn<MT, 4>(in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s); return true;
     }
     return false;
-}
-template <int NT>
-void bwd_nt(const float* dout, int B, int H, int W, int Cout, const unsigned short* wd, int Cin, float* din, dim3 g,
-            hipStream_t s) {
-    hipLaunchKernelGGL((k_conv_bwd_data<NT>), g, dim3(64), 0, s, dout, B, H, W, Cout, wd, Cin, din);
 }
 
 bool shape_ok(int B, int H, int W, int Cin, int Cout) {
@@ -509,18 +462,9 @@ int eelbm_cno_conv_fwd(const float* in, int32_t B, int32_t H, int32_t W, int32_t
 int eelbm_cno_conv_bwd_data(const float* dout, int32_t B, int32_t H, int32_t W, int32_t Cout, const uint16_t* wd,
                             int32_t Cin, float* din, void* stream) {
     if (!dout || !wd || !din || !shape_ok(B, H, W, Cout, Cin)) return EELBM_E_PARAM;
-    int nt, gy;
-    tiles(Cin, &nt, &gy);
-    const dim3 g((unsigned)((long long)B * H * ((W + 15) / 16)), (unsigned)gy);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    switch (nt) {
-#define CASE(N) \
-    case N: bwd_nt<N>(dout, B, H, W, Cout, wd, Cin, din, g, s); break;
-        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12)
-#undef CASE
-        default: return EELBM_E_PARAM;
-    }
-    return last_rc(hipGetLastError());
+    // a forward convolution of dout (Cout channels) into Cin channels with
+    // the tap-reversed weights Wd, no bias, no activation
+    return eelbm_cno_conv_fwd(dout, B, H, W, Cout, wd, nullptr, Cin, din, 0, 0.f, stream);
 }
 
 int eelbm_cno_conv_bwd_weight(const float* in, const float* dout, int32_t B, int32_t H, int32_t W, int32_t Cin,
@@ -530,7 +474,7 @@ int eelbm_cno_conv_bwd_weight(const float* in, const float* dout, int32_t B, int
     const long long P = (long long)B * H * W;
     const int chunk = 2048;
     const long long nk = (P + chunk - 1) / chunk;
-    if (nk > 65535) return EELBM_E_PARAM;
+    if (nk > 65535 || P + chunk >= (1ll << 31)) return EELBM_E_PARAM;
     hipLaunchKernelGGL(k_conv_bwd_weight, dim3((unsigned)(9 * Cin / 16), (unsigned)(Cout / 16), (unsigned)nk),
                        dim3(64), 0, s, in, dout, B, H, W, Cin, Cout, chunk, dw);
     hipError_t e = hipGetLastError();

@@ -70,6 +70,41 @@ def test_batch_equals_members_alone(graph_steps, storage):
             assert abs(da["alpha_g"] - db["alpha_g"]) < 1e-9
 
 
+def reversed_channel():
+    """A small D2Q9 channel with the flow along -x (outlet at x = 0, inlet at
+    the last column, walls on y): not the standard column, so its steps take
+    the step instantiation that reads the boundary types at run time."""
+    cfg = workloads._base("D2Q9", nx=30, ny=20, rho_l=20.0, drag="cgw", kappa_I=2e-3, g_hat=1e-6, up_axis=0,
+                          gamma=1.0, n_gamma=5, bc={"x-": "outlet", "x+": "inlet", "y-": "wall", "y+": "wall"},
+                          alpha_in_max=0.2, alpha_in_min=0.02, ug_in_max=4e-3, ug_in_min=4e-4, ul_in_max=1e-3,
+                          ul_in_min=1e-4, n_ramp=30.0)
+    f = workloads.smooth_random_2d(30, 20, seed=12, alpha0=0.1, amp_a=0.05)
+    f["inlet_noise"] = 1.0 + 0.1 * np.random.default_rng(3).uniform(-1, 1, 20)
+    return cfg, f
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_batch_of_mixed_boundary_layouts(storage):
+    # standard columns batched with a reversed channel: the batch runs the
+    # run-time boundary instantiation for every member, the members alone
+    # run their own (compile-time column / run-time), and in 2D the two give
+    # the same bits
+    from paper_2409_10399_amd import Batch
+    ws = members()[:3] + [reversed_channel()]
+    alone = _lattices(ws, storage)
+    batched = _lattices(ws, storage)
+    batch = Batch(batched, tile=(64, 4))
+    for n in (7, 12):
+        batch.advance(n)
+        for lat in alone:
+            lat.set_launch(64, 4)
+            lat.advance(n)
+        for i, (a, b) in enumerate(zip(alone, batched)):
+            for k in FIELDS:
+                assert np.array_equal(a.read(k), b.read(k)), (i, n, k)
+            assert b.diag()["nonfinite"] == 0
+
+
 @pytest.mark.parametrize("storage", ["fp32", "bf16"])
 def test_batch_equals_members_alone_d3q19(storage):
     from paper_2409_10399_amd import Batch
