@@ -177,14 +177,18 @@ def diffusivities(inst):
                         device="cuda")
 
 
-def train(net, snaps, cond, norm, lag, epochs, bsz, lr, log, keep, noise=0.0):
+def train(net, snaps, cond, norm, lag, epochs, bsz, lr, log, keep, noise=0.0, pushforward=0.0):
     """Adam with cosine decay on random pairs; noise > 0 adds Gaussian noise
     of that standard deviation (normalised units) to the input fields, so
     that the network learns to correct perturbed states such as its own
-    earlier predictions."""
+    earlier predictions.  pushforward > 0: that fraction of the batches
+    starts one jump earlier and feeds the network its own prediction of the
+    input state (no gradient through that first jump), with the true state
+    one jump later as the target, so that it learns to correct its own
+    errors."""
     import torch
     from paper_2409_10399_amd.binding import lib
-    from paper_2409_10399_amd.surrogate import _p, _stream, pack_input
+    from paper_2409_10399_amd.surrogate import _p, _stream, apply_output, pack_input
     S, N = snaps.shape[:2]
     pairs = [(s, i) for s in range(S - lag) for i in keep]
     rng = np.random.default_rng(0)
@@ -199,9 +203,14 @@ def train(net, snaps, cond, norm, lag, epochs, bsz, lr, log, keep, noise=0.0):
         acc = torch.zeros((), dtype=torch.float64, device="cuda")
         for k in range(steps_per_epoch):
             idx = [pairs[j] for j in order[k * bsz:(k + 1) * bsz]]
-            f0 = torch.stack([snaps[s, i] for s, i in idx]).contiguous()
+            push = pushforward > 0 and rng.random() < pushforward and all(s >= lag for s, _ in idx)
             f1 = torch.stack([snaps[s + lag, i] for s, i in idx]).contiguous()
             c = torch.stack([cond[i] for _, i in idx]).contiguous()
+            if push:
+                fm = torch.stack([snaps[s - lag, i] for s, i in idx]).contiguous()
+                f0 = apply_output(fm, net.forward(pack_input(fm, norm.mean, norm.inv, c, net.cin)), norm.dscale)
+            else:
+                f0 = torch.stack([snaps[s, i] for s, i in idx]).contiguous()
             x = pack_input(f0, norm.mean, norm.inv, c, net.cin)
             if noise > 0:
                 eps = torch.zeros_like(x)
@@ -286,6 +295,8 @@ def main():
     ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--alpha-weight", type=float, default=3.0)
     ap.add_argument("--noise", type=float, default=0.0)
+    ap.add_argument("--pushforward", type=float, default=0.0,
+                    help="fraction of batches fed the network's own one-jump prediction as input")
     ap.add_argument("--widths", default="32,48,96,192")
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--defect-max", type=float, default=1e-3)
@@ -339,7 +350,8 @@ def main():
         report["loss_history"] = None
         log(f"# weights loaded from {a.load_weights}")
     else:
-        report["loss_history"] = train(net, snaps, cond, norm, lag, a.epochs, a.batch, a.lr, log, keep, a.noise)
+        report["loss_history"] = train(net, snaps, cond, norm, lag, a.epochs, a.batch, a.lr, log, keep, a.noise,
+                                       a.pushforward)
     report["train_seconds"] = time.time() - T
     del snaps
     torch.cuda.empty_cache()
