@@ -171,8 +171,11 @@ int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g,
 /* Rebuild the state at time t from macroscopic fields (the layout of
  * eelbm_init_fields): populations at the local equilibria of the fields as at
  * initialisation, the inlet ramp continuing from t, the inlet noise, the
- * buoyancy reference and the lag fields of the run kept.  For restarting the
- * scheme from fields predicted elsewhere (the surrogate's re-anchoring).
+ * buoyancy reference, the reference gas fraction of the f_alpha deviations
+ * and the lag fields of the run kept (nothing is read back: with
+ * on_device = 1 the call does not wait for the device).  For restarting the
+ * scheme from fields predicted elsewhere (the surrogate's re-anchoring); a
+ * batch holding the lattice follows the new time at its next advance.
  * EELBM_E_STATE before eelbm_init_fields. */
 int eelbm_reinit_fields(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u_g, const double* u_l,
                         const double* dp_k, int on_device);

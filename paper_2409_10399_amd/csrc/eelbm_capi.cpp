@@ -422,10 +422,11 @@ int init_impl(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u
         if (rc) return rc;
     }
     // mean initial gas fraction: reference of the f_alpha deviations and,
-    // for EELBM_RHOREF_MIXTURE_MEAN, of the buoyancy reference density
+    // for EELBM_RHOREF_MIXTURE_MEAN, of the buoyancy reference density (a
+    // rebuild keeps both: no read-back, no synchronisation)
     const eelbm_params& p = h->p;
-    double am = 0.0;
-    {
+    double am = h->alpha_ref;
+    if (!keep) {
         double* sp = reinterpret_cast<double*>(h->mem + h->L.spart);
         double* so = reinterpret_cast<double*>(h->mem + h->L.dout) + kNDiag;
         e = launch_sum(stage, (long long)n, sp, 1024, so, h->stream);
@@ -437,7 +438,7 @@ int init_impl(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u
         am = sum / (double)n;
     }
     if (!std::isfinite(am)) return fail(EELBM_E_NONFINITE, "non-finite initial gas fraction");
-    h->alpha_ref = p.storage == EELBM_FP64 ? am : (double)(float)am;
+    if (!keep) h->alpha_ref = p.storage == EELBM_FP64 ? am : (double)(float)am;
     if (keep) {
         // buoyancy reference of the run
     } else if (p.rho_ref_mode == EELBM_RHOREF_LIQUID) {
@@ -726,6 +727,7 @@ struct eelbm_batch {
     int graph_steps;
     hipGraphExec_t exec;
     int exec_steps;
+    long long t_clock;  // time the device clock holds (members may be rebuilt at another time between advances)
 };
 
 namespace {
@@ -848,6 +850,7 @@ int eelbm_batch_create(eelbm_handle* const* members, int32_t n, int32_t tile_x, 
                            b->own);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->mem + b->off_clock, &t0, sizeof(t0), hipMemcpyHostToDevice, b->own);
+    b->t_clock = t0;
     if (e == hipSuccess) e = hipStreamSynchronize(b->own);
     if (e != hipSuccess) {
         delete b;
@@ -875,6 +878,14 @@ int eelbm_batch_advance(eelbm_batch* b, int64_t nsteps) {
     hipError_t e = hipEventRecord(b->ev_in, b->user);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->own, b->ev_in, 0);
     if (e != hipSuccess) return hip_fail(e, "batch stream ordering");
+    if (t0 != b->t_clock) {
+        // the members were rebuilt at another time (eelbm_reinit_fields):
+        // move the device clock there before any step
+        long long* clock = reinterpret_cast<long long*>(b->mem + b->off_clock);
+        e = launch_clock_add(clock, t0 - b->t_clock, b->own);
+        if (e != hipSuccess) return hip_fail(e, "batch clock launch");
+        b->t_clock = t0;
+    }
     int64_t left = nsteps;
     const int K = b->graph_steps;
     if (K > 0 && left >= K) {
@@ -915,6 +926,7 @@ int eelbm_batch_advance(eelbm_batch* b, int64_t nsteps) {
         h->cur = (int)(h->t & 1);
         h->diag_blocks = h->g.nblocks;
     }
+    b->t_clock += nsteps;
     return EELBM_OK;
 }
 

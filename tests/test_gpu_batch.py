@@ -105,6 +105,34 @@ def test_batch_of_mixed_boundary_layouts(storage):
             assert b.diag()["nonfinite"] == 0
 
 
+def test_batch_follows_members_rebuilt_at_another_time():
+    # members rebuilt from their own fields at t = 41 (odd, while the batch's
+    # device clock stood at 6): the next advance must run steps 42.. on the
+    # right ping-pong buffers with the inlet ramp at the new time, exactly as
+    # the lattices rebuilt and advanced alone
+    import torch
+    from paper_2409_10399_amd import Batch
+    ws = members()[:3]
+    alone = _lattices(ws, "fp32")
+    batched = _lattices(ws, "fp32")
+    batch = Batch(batched, tile=(64, 4))
+    batch.advance(6)
+    for a in alone:
+        a.set_launch(64, 4)
+        a.advance(6)
+    for lat in alone + batched:
+        f = {k: torch.tensor(lat.read(k), dtype=torch.float64, device="cuda") for k in ("alpha_g", "u_g", "u_l", "dp_k")}
+        lat.reinit_fields_device(41, f)
+    batch.advance(9)
+    for a in alone:
+        a.advance(9)
+    for i, (a, b) in enumerate(zip(alone, batched)):
+        assert a.t == b.t == 50
+        for k in FIELDS:
+            assert np.array_equal(a.read(k), b.read(k)), (i, k)
+        assert b.diag()["nonfinite"] == 0
+
+
 @pytest.mark.parametrize("storage", ["fp32", "bf16"])
 def test_batch_equals_members_alone_d3q19(storage):
     from paper_2409_10399_amd import Batch
