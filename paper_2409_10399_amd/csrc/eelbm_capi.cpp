@@ -170,6 +170,10 @@ size_t pop_plane_elems(const eelbm_params& p, const Geometry& g) {
 }
 size_t pop_bytes(const eelbm_params& p, const Geometry& g) { return (size_t)p.nz * pop_plane_elems(p, g) * g.tsize; }
 
+// MI355X's last-level (Infinity) cache: populations written in one step are
+// found there in the next when one set of them is smaller
+constexpr size_t kLastLevelCacheBytes = 256ull << 20;
+
 // imposed-velocity region of one ping-pong copy: [n] 4-wide records, then
 // [n] alpha_l values (used only without renormalisation)
 size_t cf_records_bytes(const Geometry& g) { return align256(4 * (size_t)g.n * g.csize); }
@@ -274,6 +278,7 @@ void fill_kparams(eelbm_handle* h) {
     k.use_lag = p.n_gamma > 1;
     k.renorm = !(p.flags & EELBM_FLAG_NO_RENORM);
     k.sigma_grad = !(p.flags & EELBM_FLAG_NO_SIGMA_GRAD);
+    k.nt_store = pop_bytes(p, h->g) > kLastLevelCacheBytes;
     k.R = p.rho_l / p.rho_g;
     k.invR = p.rho_g / p.rho_l;
     k.rho_g = p.rho_g;
@@ -728,6 +733,7 @@ struct eelbm_batch {
     hipGraphExec_t exec;
     int exec_steps;
     long long t_clock;  // time the device clock holds (members may be rebuilt at another time between advances)
+    bool nt_store;      // the members' populations together exceed the last-level cache
 };
 
 namespace {
@@ -774,7 +780,7 @@ int batch_step_launches(eelbm_batch* b, int64_t nsteps, hipStream_t s) {
     const uint2* work = reinterpret_cast<const uint2*>(b->mem + b->off_work);
     long long* clock = reinterpret_cast<long long*>(b->mem + b->off_clock);
     for (int64_t k = 0; k < nsteps; ++k) {
-        hipError_t e = launch_batch_step(b->lattice, b->storage, b->bc_mode, lat, work, b->nwork, clock, (int)k,
+        hipError_t e = launch_batch_step(b->lattice, b->storage, b->bc_mode, b->nt_store, lat, work, b->nwork, clock, (int)k,
                                          k == nsteps - 1, b->block, s);
         if (e != hipSuccess) return hip_fail(e, "batch step launch");
     }
@@ -808,6 +814,7 @@ int eelbm_batch_create(eelbm_handle* const* members, int32_t n, int32_t tile_x, 
     if (z.nwork >= (1ll << 31)) return fail(EELBM_E_PARAM, "too many tiles in one batch");
     // every member takes the batch's tile shape (its own launches use it too)
     std::vector<BatchLattice> lat((size_t)n);
+    size_t batch_pop = 0;
     std::vector<uint2> work;
     work.reserve((size_t)z.nwork);
     for (int32_t i = 0; i < n; ++i) {
@@ -815,12 +822,16 @@ int eelbm_batch_create(eelbm_handle* const* members, int32_t n, int32_t tile_x, 
         set_tiles(h->p, &h->g, tile_x, tile_y, h->g.xcd_remap);
         fill_kparams(h);
         lat[i].p = h->kp;
+        batch_pop += pop_bytes(h->p, h->g);
         lat[i].buf[0] = buffers(h, 0, 1);
         lat[i].buf[1] = buffers(h, 1, 0);
         for (int t = 0; t < h->g.nblocks; ++t) work.push_back(make_uint2((unsigned)i, (unsigned)t));
     }
+    // one step of the batch writes the populations of every member
+    for (auto& l : lat) l.p.nt_store = batch_pop > kLastLevelCacheBytes;
     eelbm_batch* b = new (std::nothrow) eelbm_batch();
     if (!b) return fail(EELBM_E_PARAM, "out of host memory");
+    b->nt_store = batch_pop > kLastLevelCacheBytes;
     b->m.assign(members, members + n);
     b->lattice = members[0]->p.lattice;
     b->storage = members[0]->p.storage;

@@ -28,6 +28,7 @@ struct KParams {
     int use_lag;        // n_gamma > 1: lag fields are stored
     int renorm;         // Spalding renormalisation on?
     int sigma_grad;     // sigma . grad(alpha) / alpha term on?
+    int nt_store;       // the launches store populations with the nontemporal hint (one set larger than the last-level cache)
     double R, invR, rho_g, rho_l;
     double omega_g, omega_l, psi_g, psi_l, omega_ag, omega_al;
     double K_I, kappa_I, K_W;
@@ -83,7 +84,7 @@ constexpr int kBcColumn = 2;
 hipError_t launch_step(int lattice, int storage, int bc, bool init, const KParams& p,
                        const KBuffers& b, const KCtl& c, dim3 grid, dim3 block, hipStream_t s);
 // one step of every lattice of a batch: grid = work items (lattice, tile)
-hipError_t launch_batch_step(int lattice, int storage, int bc, const BatchLattice* lat, const uint2* work,
+hipError_t launch_batch_step(int lattice, int storage, int bc, bool nts, const BatchLattice* lat, const uint2* work,
                              long long nwork, const long long* clock, int k, int write_last, dim3 block,
                              hipStream_t s);
 hipError_t launch_clock_add(long long* clock, long long add, hipStream_t s);

@@ -102,7 +102,10 @@ __device__ __forceinline__ void st_rec(__amdgpu_buffer_rsrc_t r, unsigned vo, co
 // The hot streams use buffer instructions: a descriptor in SGPRs, one VGPR
 // byte offset shared by every access of a node, and the per-direction shift
 // in an SGPR offset, so an access costs no vector ALU work.  Bit 1 of the
-// cache-policy operand is the nontemporal hint on gfx950.
+// cache-policy operand is the nontemporal hint on gfx950.  Populations are
+// always loaded with it; they are stored with it only when the lattice's
+// populations do not fit the last-level cache (KParams::nt_store): a smaller
+// lattice finds the populations written in one step there in the next.
 constexpr int kNT = 2;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
@@ -125,9 +128,10 @@ struct Pop4<float> {
         o[2] = v.z;
         o[3] = v.w;
     }
+    template <int POL>
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const float* v) {
         const f32x4 w = {v[0], v[1], v[2], v[3]};
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, w), r, (int)vo, (int)so, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, w), r, (int)vo, (int)so, POL);
     }
 };
 template <>
@@ -141,10 +145,11 @@ struct Pop4<double> {
         o[2] = b.x;
         o[3] = b.y;
     }
+    template <int POL>
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const double* v) {
         const f64x2 a = {v[0], v[1]}, b = {v[2], v[3]};
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, a), r, (int)vo, (int)so, 0);
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, b), r, (int)vo, (int)(so + 16), 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, a), r, (int)vo, (int)so, POL);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, b), r, (int)vo, (int)(so + 16), POL);
     }
 };
 // 16-bit storage: set k sits in half-word k of the 8-byte group.  FP16 holds
@@ -176,11 +181,12 @@ struct Pop4Half {
         o[2] = to_f((unsigned short)(v.y & 0xffffu));
         o[3] = to_f((unsigned short)(v.y >> 16));
     }
+    template <int POL>
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const float* v) {
         u32x2 w;
         w.x = (unsigned)from_f(v[0]) | ((unsigned)from_f(v[1]) << 16);
         w.y = (unsigned)from_f(v[2]) | ((unsigned)from_f(v[3]) << 16);
-        __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)vo, (int)so, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)vo, (int)so, POL);
     }
 };
 template <>
@@ -288,7 +294,7 @@ __device__ __forceinline__ double ramp(double t, double ymax, double ymin, doubl
 // them); the steps that never write them run an instantiation without that
 // code, which needs fewer registers (D2Q9 FP32 channel: 88 instead of 99
 // VGPRs, 5 waves per SIMD instead of 4) and computes the same bits.
-template <class L, class T, int BC, bool INIT, bool OUT = true>
+template <class L, class T, int BC, bool INIT, bool OUT = true, bool NTS = false>
 __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, const KCtl& ctl, long long tile,
                                           long long part) {
     using C = typename Compute<T>::C;
@@ -865,7 +871,8 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                 const C o2 = koa * f[2][q] + wq * (Aa + Ba * sg2);
                 const C o3 = kob * f[3][q] + wq * (Ab + Bb * sl2);
                 const C o4[4] = {o0, o1, o2, o3};
-                Pop4<T>::st(ro, vl + (unsigned)((oblk + q * 256) * (long long)sizeof(T)), 0u, o4);
+                const unsigned vq = vl + (unsigned)((oblk + q * 256) * (long long)sizeof(T));
+                Pop4<T>::template st<NTS ? kNT : 0>(ro, vq, 0u, o4);
             }
         }
 
@@ -977,16 +984,16 @@ __device__ __forceinline__ long long xcd_tile(long long id, long long nb, int re
     return id < per * 8 ? (id & 7) * per + (id >> 3) : id;
 }
 
-template <class L, class T, int BC, bool INIT, bool OUT>
+template <class L, class T, int BC, bool INIT, bool OUT, bool NTS>
 __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b, const KCtl ctl) {
-    step_body<L, T, BC, INIT, OUT>(p, b, ctl, xcd_tile(blockIdx.x, gridDim.x, p.xcd_remap), blockIdx.x);
+    step_body<L, T, BC, INIT, OUT, NTS>(p, b, ctl, xcd_tile(blockIdx.x, gridDim.x, p.xcd_remap), blockIdx.x);
 }
 
 // Batched step: one launch advances every lattice of a batch by one step.
 // Work item w = (lattice, tile); each lattice brings its own parameters and
 // both ping-pong buffer sets; the step's time is the batch clock + k + 1, so
 // a captured sequence of launches replays correctly at any time.
-template <class L, class T, int BC, bool OUT>
+template <class L, class T, int BC, bool OUT, bool NTS>
 __global__ void __launch_bounds__(256) k_step_batch(const BatchLattice* lat, const uint2* work,
                                                     const long long* clock, int k, int write_last) {
     const uint2 w = work[xcd_tile(blockIdx.x, gridDim.x, 1)];
@@ -998,7 +1005,7 @@ __global__ void __launch_bounds__(256) k_step_batch(const BatchLattice* lat, con
     c.write_macro = write_last;
     c.write_diag = write_last;
     const KBuffers bb = d.buf[(c.t - 1) & 1];
-    step_body<L, T, BC, false, OUT>(p, bb, c, w.y, w.y);
+    step_body<L, T, BC, false, OUT, NTS>(p, bb, c, w.y, w.y);
 }
 
 __global__ void k_clock_add(long long* clock, long long add) {
@@ -1049,9 +1056,9 @@ __global__ void __launch_bounds__(256) k_convert(const double* src, void* dst, i
 }
 
 // ------------------------------------------------------------ launchers
-template <class L, class T, int BC, bool INIT, bool OUT>
+template <class L, class T, int BC, bool INIT, bool OUT, bool NTS = false>
 static hipError_t go(const KParams& p, const KBuffers& b, const KCtl& c, dim3 g, dim3 bl, hipStream_t s) {
-    hipLaunchKernelGGL((k_step<L, T, BC, INIT, OUT>), g, bl, 0, s, p, b, c);
+    hipLaunchKernelGGL((k_step<L, T, BC, INIT, OUT, NTS>), g, bl, 0, s, p, b, c);
     return hipGetLastError();
 }
 
@@ -1062,8 +1069,13 @@ template <class L, class T, int BC>
 static hipError_t go3(bool init, const KParams& p, const KBuffers& b, const KCtl& c, dim3 g, dim3 bl,
                       hipStream_t s) {
     if (init) return go<L, T, BC == kBcColumn ? kBcGeneric : BC, true, true>(p, b, c, g, bl, s);
-    if (c.write_diag || c.write_macro) return go<L, T, BC, false, true>(p, b, c, g, bl, s);
-    return go<L, T, BC, false, false>(p, b, c, g, bl, s);
+    // a lattice whose populations exceed the last-level cache stores them
+    // with the nontemporal hint
+    if (c.write_diag || c.write_macro)
+        return p.nt_store ? go<L, T, BC, false, true, true>(p, b, c, g, bl, s)
+                          : go<L, T, BC, false, true, false>(p, b, c, g, bl, s);
+    return p.nt_store ? go<L, T, BC, false, false, true>(p, b, c, g, bl, s)
+                      : go<L, T, BC, false, false, false>(p, b, c, g, bl, s);
 }
 
 template <class L, class T>
@@ -1096,19 +1108,19 @@ hipError_t launch_step(int lattice, int storage, int bc, bool init, const KParam
     return hipErrorInvalidValue;
 }
 
-template <class L, class T, bool OUT>
+template <class L, class T, bool OUT, bool NTS>
 static hipError_t gob_out(int bc, const BatchLattice* lat, const uint2* work, long long nwork,
                           const long long* clock, int k, int write_last, dim3 block, hipStream_t s) {
     const dim3 g((unsigned)nwork);
     switch (bc) {
         case kBcPeriodic:
-            hipLaunchKernelGGL((k_step_batch<L, T, kBcPeriodic, OUT>), g, block, 0, s, lat, work, clock, k, write_last);
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcPeriodic, OUT, NTS>), g, block, 0, s, lat, work, clock, k, write_last);
             break;
         case kBcGeneric:
-            hipLaunchKernelGGL((k_step_batch<L, T, kBcGeneric, OUT>), g, block, 0, s, lat, work, clock, k, write_last);
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcGeneric, OUT, NTS>), g, block, 0, s, lat, work, clock, k, write_last);
             break;
         case kBcColumn:
-            hipLaunchKernelGGL((k_step_batch<L, T, kBcColumn, OUT>), g, block, 0, s, lat, work, clock, k, write_last);
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcColumn, OUT, NTS>), g, block, 0, s, lat, work, clock, k, write_last);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -1116,29 +1128,32 @@ static hipError_t gob_out(int bc, const BatchLattice* lat, const uint2* work, lo
 }
 
 template <class L, class T>
-static hipError_t gob(int bc, const BatchLattice* lat, const uint2* work, long long nwork, const long long* clock,
-                      int k, int write_last, dim3 block, hipStream_t s) {
-    return write_last ? gob_out<L, T, true>(bc, lat, work, nwork, clock, k, write_last, block, s)
-                      : gob_out<L, T, false>(bc, lat, work, nwork, clock, k, write_last, block, s);
+static hipError_t gob(int bc, bool nts, const BatchLattice* lat, const uint2* work, long long nwork,
+                      const long long* clock, int k, int write_last, dim3 block, hipStream_t s) {
+    if (nts)
+        return write_last ? gob_out<L, T, true, true>(bc, lat, work, nwork, clock, k, write_last, block, s)
+                          : gob_out<L, T, false, true>(bc, lat, work, nwork, clock, k, write_last, block, s);
+    return write_last ? gob_out<L, T, true, false>(bc, lat, work, nwork, clock, k, write_last, block, s)
+                      : gob_out<L, T, false, false>(bc, lat, work, nwork, clock, k, write_last, block, s);
 }
 
 template <class L>
-static hipError_t gob1(int storage, int bc, const BatchLattice* lat, const uint2* work, long long nwork,
+static hipError_t gob1(int storage, int bc, bool nts, const BatchLattice* lat, const uint2* work, long long nwork,
                        const long long* clock, int k, int write_last, dim3 block, hipStream_t s) {
     switch (storage) {
-        case EELBM_FP64: return gob<L, double>(bc, lat, work, nwork, clock, k, write_last, block, s);
-        case EELBM_FP32: return gob<L, float>(bc, lat, work, nwork, clock, k, write_last, block, s);
-        case EELBM_FP16: return gob<L, __half>(bc, lat, work, nwork, clock, k, write_last, block, s);
-        case EELBM_BF16: return gob<L, __hip_bfloat16>(bc, lat, work, nwork, clock, k, write_last, block, s);
+        case EELBM_FP64: return gob<L, double>(bc, nts, lat, work, nwork, clock, k, write_last, block, s);
+        case EELBM_FP32: return gob<L, float>(bc, nts, lat, work, nwork, clock, k, write_last, block, s);
+        case EELBM_FP16: return gob<L, __half>(bc, nts, lat, work, nwork, clock, k, write_last, block, s);
+        case EELBM_BF16: return gob<L, __hip_bfloat16>(bc, nts, lat, work, nwork, clock, k, write_last, block, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_step(int lattice, int storage, int bc, const BatchLattice* lat, const uint2* work,
+hipError_t launch_batch_step(int lattice, int storage, int bc, bool nts, const BatchLattice* lat, const uint2* work,
                              long long nwork, const long long* clock, int k, int write_last, dim3 block,
                              hipStream_t s) {
-    if (lattice == EELBM_D2Q9) return gob1<D2Q9>(storage, bc, lat, work, nwork, clock, k, write_last, block, s);
-    if (lattice == EELBM_D3Q19) return gob1<D3Q19>(storage, bc, lat, work, nwork, clock, k, write_last, block, s);
+    if (lattice == EELBM_D2Q9) return gob1<D2Q9>(storage, bc, nts, lat, work, nwork, clock, k, write_last, block, s);
+    if (lattice == EELBM_D3Q19) return gob1<D3Q19>(storage, bc, nts, lat, work, nwork, clock, k, write_last, block, s);
     return hipErrorInvalidValue;
 }
 
