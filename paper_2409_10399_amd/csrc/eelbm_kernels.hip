@@ -351,7 +351,12 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
         bool fix = false;
 #pragma unroll
         for (int a = 0; a < D; ++a) fix = fix || co[a] == 0 || co[a] == nn[a] - 1;
-        const bool general = INIT || __any(fix);
+        // The interior gather (one block-relative offset per x-shift, shared by
+        // every direction) is kept only where it pays: its registers cost more
+        // waves per SIMD than its addressing saves everywhere except the
+        // periodic D3Q19 step in 16-bit storage (measured).
+        constexpr bool kFastGather = L::D == 3 && BC == kBcPeriodic && sizeof(T) == 2;
+        const bool general = INIT || !kFastGather || __any(fix);
 
         // -------------------------------------------------- boundary layout
         bool lo[3] = {false, false, false}, hi[3] = {false, false, false};
