@@ -258,12 +258,14 @@ def _shift_fields(f, k):
 @pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
 def test_fast_gather_matches_general_bitwise(lattice, storage):
     """A periodic lattice three 64-node x-blocks wide, run twice: once as is
-    and once with its initial fields shifted by one x-block.  The interior
-    block's nodes, computed by the fast gather in one run, are computed by the
-    general (wrap-around) gather in the other, so every field must agree bit
-    for bit after the shift -- in every storage type, with no tolerance.  The
-    gas fraction is quantised to 2^-12 so that its mean, which sets the base
-    of the stored deviations, is exact in any summation order."""
+    and once with its initial fields shifted by one x-block.  Where the step
+    has an interior gather (periodic D3Q19 in 16-bit storage), the interior
+    block's nodes take it in one run and the general (wrap-around) gather in
+    the other; elsewhere every node takes the general gather and the test
+    checks its translation invariance.  Every field must agree bit for bit
+    after the shift, with no tolerance.  The gas fraction is quantised to
+    2^-12 so that its mean, which sets the base of the stored deviations, is
+    exact in any summation order."""
     if lattice == "D2Q9":
         nx, ny = 192, 16
         cfg = workloads._base("D2Q9", nx=nx, ny=ny, rho_l=10.0, drag="cgw", kappa_I=2e-3, g_hat=1e-5,
