@@ -27,6 +27,22 @@ def to_bf16(x):
     return r.view(np.float32).astype(np.float64)
 
 
+def fp32_floor(cfg, f, steps):
+    """rel-L2 per field of the oracle with its stored deviations rounded to
+    FP32 after every step, against the plain oracle."""
+    ref, em = Oracle(cfg, f), Oracle(cfg, f)
+    w = ref.lat.w.reshape((-1,) + (1,) * (ref.f["g"].ndim - 1))
+    ar = float(np.mean(f["alpha_g"]))
+    bases = (("g", w), ("l", w), ("ag", w * ar), ("al", w * (1 - ar)))
+    for _ in range(steps):
+        ref.step(1)
+        em.step(1)
+        for s, base in bases:
+            em.f[s] = base + (em.f[s] - base).astype(np.float32).astype(np.float64)
+    ro, re = ref.read(), em.read()
+    return {k: np.linalg.norm(re[k] - ro[k]) / np.linalg.norm(ro[k]) for k in ("alpha_g", "u_g", "u_l", "dp_k")}
+
+
 def floors(cfg, f, steps, kinds):
     """Print the per-field rel-L2 floor of each storage kind after `steps`."""
     ref = Oracle(cfg, f)

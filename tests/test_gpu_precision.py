@@ -55,3 +55,36 @@ def test_storage_precision_channel(nx, ny):
 def test_storage_precision_column():
     cfg, f = workloads.column_3d(n=32, nblobs=2)
     _check(cfg, f, 200, COLUMN)
+
+
+CROP64 = {  # 64^3 crop of the 256^3 column workload (256 blobs), 20 steps
+    "fp32": {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5},  # dp_k: 10 x the FP32 storage floor
+    "fp16": {"alpha_g": 5e-4, "u_g": 3e-3, "u_l": 0.3, "dp_k": 40.0},
+    "bf16": {"alpha_g": 2.5e-3, "u_g": 3.5e-3, "u_l": 2e-2, "dp_k": 40.0},
+}
+
+
+def test_storage_precision_column_crop64():
+    """The 256^3 column's own fields, a 64^3 crop run as a periodic box: every
+    storage type against the FP64 oracle, and the 16-bit types against FP32
+    storage (printed).  In FP32, delta p_k (1e-4 of the deviation scale at
+    rest) is bounded by 10 x the storage floor of the oracle with its
+    deviations rounded to FP32 every step (1.0e-2 here; GPU 4.0e-2)."""
+    from storage_floor import fp32_floor
+    cfg, f = workloads.column_3d(n=256, nblobs=256)
+    crop = {k: np.ascontiguousarray(v[..., :64, :64, :64]) for k, v in f.items()}
+    cfg = dict(cfg, nx=64, ny=64, nz=64)
+    steps = 20
+    ro = run_oracle(cfg, crop, steps).read()
+    floor = fp32_floor(cfg, crop, steps)
+    g = {}
+    for storage, tol in CROP64.items():
+        g[storage] = run_gpu(cfg, crop, steps, storage).read_all()
+        errs = {k: rel_l2(g[storage][k], ro[k]) for k in FIELDS}
+        print(f"  {storage} " + " ".join(f"{k}={errs[k]:.2e}" for k in FIELDS), flush=True)
+        for k in FIELDS:
+            bound = tol.get(k, 10.0 * floor[k])
+            assert np.isfinite(errs[k]) and errs[k] <= bound, (storage, k, errs[k], bound)
+    for storage in ("fp16", "bf16"):
+        print(f"  {storage} vs fp32 storage " + " ".join(f"{k}={rel_l2(g[storage][k], g['fp32'][k]):.2e}" for k in FIELDS),
+              flush=True)
