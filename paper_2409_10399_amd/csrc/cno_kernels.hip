@@ -57,6 +57,7 @@ template <int MT, int NT>
 __global__ void __launch_bounds__(64) k_conv_fwd(const float* __restrict__ in, int B, int H, int W, int Cin,
                                                 const unsigned short* __restrict__ wf, const float* __restrict__ bias,
                                                 int Cout, float* __restrict__ out, int act, float slope) {
+    (void)B;  // the grid covers the B * H image rows
     const int lane = threadIdx.x;
     const int gw = (W + 16 * MT - 1) / (16 * MT);
     const long long grp = blockIdx.x;
