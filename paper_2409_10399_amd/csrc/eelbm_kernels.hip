@@ -27,10 +27,12 @@
 //    values the boundary extrapolations of Eqs. (160)-(161) need at the next
 //    step (u_g, u_l, alpha_g, alpha_l, S_g, S_l).
 //
-// Wavefronts whose nodes all pull from interior neighbours take a fast
-// gather: every load is a wave-uniform base plus one shared 32-bit node
-// offset.  Wavefronts touching a face (periodic wrap or a boundary rule) take
-// the general gather.
+// The general gather computes every pulled node per lane (periodic wrap and
+// the boundary rules included).  In the periodic D3Q19 step with 16-bit
+// storage, wavefronts whose nodes all pull from interior neighbours take an
+// interior gather instead (a wave-uniform base plus one shared 32-bit offset
+// per x-shift); elsewhere that second gather costs more in registers than it
+// saves.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
