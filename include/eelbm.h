@@ -171,9 +171,12 @@ int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g,
 /* Rebuild the state at time t from macroscopic fields (the layout of
  * eelbm_init_fields): populations at the local equilibria of the fields as at
  * initialisation, the inlet ramp continuing from t, the inlet noise, the
- * buoyancy reference, the reference gas fraction of the f_alpha deviations
- * and the lag fields of the run kept (nothing is read back: with
- * on_device = 1 the call does not wait for the device).  For restarting the
+ * buoyancy reference and the reference gas fraction of the f_alpha
+ * deviations kept (nothing is read back: with on_device = 1 the call does not
+ * wait for the device).  The lagged S''_g, S''_l and Lambda' of Sec. 3.2 and
+ * Eq. (137) are taken afresh from the rebuilt state at t, as at t = 0: the
+ * fields carry no lagged values, and the lag of the previous run belongs to
+ * another state.  For restarting the
  * scheme from fields predicted elsewhere (the surrogate's re-anchoring); a
  * batch holding the lattice follows the new time at its next advance.
  * EELBM_E_STATE before eelbm_init_fields. */
@@ -207,7 +210,11 @@ int eelbm_get_launch(const eelbm_handle* h, int32_t* tile_x, int32_t* tile_y, in
 
 /* Checkpoint: bytes needed for a save (eelbm_save with host_buf = NULL sets
  * *bytes), save to a caller host buffer, load into a handle created with the
- * same parameters.  A loaded run continues bit-for-bit like the saved one. */
+ * same parameters.  A loaded run continues bit-for-bit like the saved one.
+ * The checkpoint carries the saving handle's eelbm_params; eelbm_load returns
+ * EELBM_E_PARAM (state unchanged) when any of them differs from the loading
+ * handle's (geometry, storage, densities, relaxation rates, drag, gravity,
+ * stabilisers, boundary types or inlet ramp). */
 int eelbm_save(eelbm_handle* h, void* host_buf, size_t* bytes);
 int eelbm_load(eelbm_handle* h, const void* host_buf, size_t bytes);
 
@@ -257,7 +264,10 @@ int eelbm_batch_set_graph(eelbm_batch* b, int32_t steps_per_graph);
 /* Advance every member by nsteps (asynchronous).  The last step of the
  * advance (and of every replayed graph) writes the output fields and
  * diagnostics of every member, so eelbm_read / eelbm_diag on a member work as
- * after eelbm_advance.  EELBM_E_STATE if a member was advanced on its own. */
+ * after eelbm_advance.  EELBM_E_STATE if a member was advanced on its own,
+ * or was initialised (eelbm_init_fields), loaded, autotuned or given another
+ * launch shape after the batch copied its parameters (eelbm_reinit_fields
+ * keeps them and is followed). */
 int eelbm_batch_advance(eelbm_batch* b, int64_t nsteps);
 
 /* Release the batch (not the members or the caller's memory). */

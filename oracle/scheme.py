@@ -82,7 +82,11 @@ class Params:
 class Oracle:
     """Plain FP64 state of the six schemes on one lattice."""
 
-    def __init__(self, cfg, fields):
+    def __init__(self, cfg, fields, t0=0):
+        """Populations at time t0 rebuilt from the macroscopic fields (the
+        initial state when t0 = 0).  Reading R22: a run started (or restarted)
+        at t0 takes its lagged S'' and Lambda' at its first step, whatever
+        t0 mod n_gamma: the fields carry no lagged values to resume from."""
         p = self.p = Params(cfg)
         lat = self.lat = p.lat
         D = lat.D
@@ -125,10 +129,10 @@ class Oracle:
         c_l0 = a_g0 * (u_l0 - u_g0)
         ones = np.ones(grid)
         bvals0 = {"b_g": ones, "b_l": ones, "c_g": c_g0, "c_l": c_l0}
-        self.t = 0
-        self.f["bg"] = self._stream("bg", eq.feq_S(lat, ones, c_g0), bvals0, t=-1)
-        self.f["bl"] = self._stream("bl", eq.feq_S(lat, ones, c_l0), bvals0, t=-1)
-        self.lag = {"S2_g": np.zeros(grid), "S2_l": np.zeros(grid), "Lam": np.zeros(grid)}
+        self.t = int(t0)
+        self.f["bg"] = self._stream("bg", eq.feq_S(lat, ones, c_g0), bvals0, t=self.t - 1)
+        self.f["bl"] = self._stream("bl", eq.feq_S(lat, ones, c_l0), bvals0, t=self.t - 1)
+        self.lag = None   # taken at the first step (reading R22)
 
     # ------------------------------------------------------------------ moments
     def moments(self):
@@ -191,8 +195,9 @@ class Oracle:
         # Clift-Grace-Weber volume-fraction factor, Eq. (136).
         Lam = alpha_g * alpha_l * (alpha_g + alpha_l * p.R)
         # Lagged updates, Eqs. (133) and (137); reading R9: refresh when
-        # t mod n_gamma == 0, t = 0 included.
-        if t % p.n_gamma == 0:
+        # t mod n_gamma == 0, t = 0 included; reading R22: and at the first
+        # step of a run.
+        if t % p.n_gamma == 0 or self.lag is None:
             self.lag = {"S2_g": Sp_g.copy(), "S2_l": Sp_l.copy(), "Lam": Lam.copy()}
         S2_g, S2_l, Lam_lag = self.lag["S2_g"], self.lag["S2_l"], self.lag["Lam"]
 

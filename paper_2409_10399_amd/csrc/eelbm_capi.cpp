@@ -36,7 +36,7 @@ int hip_fail(hipError_t e, const char* what) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t pop[2], cf[2], lag, side[2], noise, stage, macro, partials, dout, spart, total;
+    size_t pop[2], cf[2], lag, side[2], noise, stage, macro, partials, dout, spart, dscr, total;
 };
 
 struct Geometry {
@@ -205,6 +205,7 @@ Layout layout(const eelbm_params& p, const Geometry& g) {
     L.partials = take(max_blocks(p) * kNDiag * 8);
     L.dout = take((kNDiag + 1) * 8);
     L.spart = take(1024 * 8);
+    L.dscr = take((size_t)kDiagGroups * kNDiag * 8);
     L.total = off;
     return L;
 }
@@ -227,6 +228,7 @@ struct eelbm_handle {
     double alpha_ref;  // mean initial gas fraction: reference of the f_alpha deviations
     int64_t diag_blocks;  // workgroups that wrote the current diagnostic partial sums
     KParams kp;
+    uint64_t gen;  // bumped when the step parameters or tiles change (init, load, launch shape)
 };
 
 namespace {
@@ -310,7 +312,9 @@ void fill_kparams(eelbm_handle* h) {
 int launch(eelbm_handle* h, bool init, int64_t t, bool last) {
     KCtl c{};
     c.t = t;
-    c.refresh = (t % h->p.n_gamma) == 0;
+    // lagged S'' and Lambda' (Eqs. (133), (137)) refresh at t mod n_gamma == 0
+    // and at the first step of a run or rebuild: fields bring no lagged values
+    c.refresh = init || (t % h->p.n_gamma) == 0;
     c.write_macro = last;
     c.write_diag = last;
     // the state at time t is always copy t mod 2
@@ -456,6 +460,7 @@ int init_impl(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u
     h->b_g = (h->rho_ref / p.rho_g - 1.0) * p.g_hat;
     h->b_l = (h->rho_ref / p.rho_l - 1.0) * p.g_hat;
     fill_kparams(h);
+    if (!keep) ++h->gen;
     rc = launch(h, true, t, true);
     if (rc) return rc;
     if (!on_device) {
@@ -500,6 +505,7 @@ int eelbm_set_launch(eelbm_handle* h, int32_t tile_x, int32_t tile_y, int32_t xc
     if (h->g.D == 2 && tile_y > h->p.ny) return fail(EELBM_E_PARAM, "tile_y exceeds ny");
     set_tiles(h->p, &h->g, tile_x, tile_y, xcd_remap ? 1 : 0);
     fill_kparams(h);
+    ++h->gen;
     return EELBM_OK;
 }
 
@@ -561,7 +567,8 @@ int eelbm_diag(eelbm_handle* h, eelbm_diagnostics* out) {
     if (!h->initialized) return fail(EELBM_E_STATE, "eelbm_init_fields not called");
     double* parts = reinterpret_cast<double*>(h->mem + h->L.partials);
     double* d = reinterpret_cast<double*>(h->mem + h->L.dout);
-    hipError_t e = launch_diag_finalize(parts, (int)h->diag_blocks, d, h->stream);
+    double* scr = reinterpret_cast<double*>(h->mem + h->L.dscr);
+    hipError_t e = launch_diag_finalize(parts, (int)h->diag_blocks, scr, d, h->stream);
     if (e != hipSuccess) return hip_fail(e, "diag launch");
     double v[kNDiag];
     e = hipMemcpyAsync(v, d, sizeof(v), hipMemcpyDeviceToHost, h->stream);
@@ -596,8 +603,17 @@ struct SaveHeader {
     double rho_ref, b_g, b_l, alpha_ref;
     int64_t diag_blocks;
     uint64_t pop_bytes, cf_bytes, lag_bytes, side_bytes, macro_bytes, part_bytes, noise_bytes;
+    eelbm_params params;  // the run's parameters (reserved field cleared): a load must match them
 };
-constexpr uint64_t kMagic = 0x45454c424d434b31ull;  // "EELBMCK1"
+constexpr uint64_t kMagic = 0x45454c424d434b32ull;  // "EELBMCK2"
+
+eelbm_params canonical(const eelbm_params& p) {
+    eelbm_params c;
+    std::memset(&c, 0, sizeof(c));
+    c = p;
+    c.reserved_i = 0;
+    return c;
+}
 
 void save_sizes(const eelbm_handle* h, SaveHeader* s) {
     const size_t n = (size_t)h->g.n;
@@ -636,6 +652,7 @@ int eelbm_save(eelbm_handle* h, void* host_buf, size_t* bytes) {
     s.b_l = h->b_l;
     s.alpha_ref = h->alpha_ref;
     s.diag_blocks = h->diag_blocks;
+    s.params = canonical(h->p);
     char* o = static_cast<char*>(host_buf);
     std::memcpy(o, &s, sizeof(s));
     o += sizeof(s);
@@ -672,6 +689,9 @@ int eelbm_load(eelbm_handle* h, const void* host_buf, size_t bytes) {
         s.cf_bytes != want.cf_bytes || s.lag_bytes != want.lag_bytes || s.side_bytes != want.side_bytes ||
         s.macro_bytes != want.macro_bytes || s.part_bytes != want.part_bytes || s.noise_bytes != want.noise_bytes)
         return fail(EELBM_E_PARAM, "checkpoint does not match this lattice");
+    const eelbm_params mine = canonical(h->p);
+    if (std::memcmp(&mine, &s.params, sizeof(mine)) != 0)
+        return fail(EELBM_E_PARAM, "checkpoint was saved with other physical or boundary parameters");
     const size_t need = sizeof(s) + s.pop_bytes + s.cf_bytes + s.lag_bytes + s.side_bytes + s.macro_bytes +
                         s.part_bytes + s.noise_bytes;
     if (bytes < need) return fail(EELBM_E_SIZE, "checkpoint truncated");
@@ -697,6 +717,7 @@ int eelbm_load(eelbm_handle* h, const void* host_buf, size_t bytes) {
     h->b_g = s.b_g;
     h->b_l = s.b_l;
     fill_kparams(h);
+    ++h->gen;
     h->initialized = true;
     return EELBM_OK;
 }
@@ -719,6 +740,7 @@ int eelbm_map_physical(double g, double kappa_I, double g_hat, double kappa_hat,
 
 struct eelbm_batch {
     std::vector<eelbm_handle*> m;
+    std::vector<uint64_t> gen;  // members' generations when the batch copied their parameters
     int lattice, storage;
     int bc_mode;  // kBc* configuration of the step kernel; members agree on it or it is kBcGeneric
     char* mem;
@@ -833,6 +855,7 @@ int eelbm_batch_create(eelbm_handle* const* members, int32_t n, int32_t tile_x, 
     if (!b) return fail(EELBM_E_PARAM, "out of host memory");
     b->nt_store = batch_pop > kLastLevelCacheBytes;
     b->m.assign(members, members + n);
+    for (int32_t i = 0; i < n; ++i) b->gen.push_back(members[i]->gen);
     b->lattice = members[0]->p.lattice;
     b->storage = members[0]->p.storage;
     b->bc_mode = members[0]->g.bc_mode;
@@ -883,8 +906,13 @@ int eelbm_batch_advance(eelbm_batch* b, int64_t nsteps) {
     if (nsteps < 0) return fail(EELBM_E_PARAM, "nsteps < 0");
     if (nsteps == 0) return EELBM_OK;
     const long long t0 = b->m[0]->t;
-    for (auto* h : b->m)
-        if (h->t != t0) return fail(EELBM_E_STATE, "a batch member was advanced on its own");
+    for (size_t i = 0; i < b->m.size(); ++i) {
+        if (b->m[i]->t != t0) return fail(EELBM_E_STATE, "a batch member was advanced on its own");
+        if (b->m[i]->gen != b->gen[i])
+            return fail(EELBM_E_STATE,
+                        "a batch member was initialised, loaded or given another launch shape after the batch was "
+                        "created: create the batch again");
+    }
     // order after the caller's stream
     hipError_t e = hipEventRecord(b->ev_in, b->user);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->own, b->ev_in, 0);
@@ -970,6 +998,7 @@ int eelbm_autotune(eelbm_handle* h, int32_t steps, int32_t force, int32_t* tile_
         if (it != cache.end() && !force) {
             set_tiles(h->p, &h->g, it->second[0], it->second[1], it->second[2]);
             fill_kparams(h);
+            ++h->gen;
             if (tile_x) *tile_x = it->second[0];
             if (tile_y) *tile_y = it->second[1];
             if (xcd_remap) *xcd_remap = it->second[2];
@@ -1022,6 +1051,7 @@ int eelbm_autotune(eelbm_handle* h, int32_t steps, int32_t force, int32_t* tile_
     (void)hipEventDestroy(e1);
     set_tiles(h->p, &h->g, pick[0], pick[1], pick[2]);
     fill_kparams(h);
+    ++h->gen;
     {
         std::lock_guard<std::mutex> lk(mu);
         cache[key] = pick;

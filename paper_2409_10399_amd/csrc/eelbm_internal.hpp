@@ -8,6 +8,10 @@
 namespace eelbm {
 
 constexpr int kNDiag = 18;  // per-node diagnostic sums (see k_step)
+// diagnostics finalize: at most kDiagGroups workgroups of the first pass, each
+// over at least kDiagRowsPerGroup block partials (scratch: kDiagGroups rows)
+constexpr int kDiagGroups = 256;
+constexpr int kDiagRowsPerGroup = 1024;
 constexpr int kMaxSideVals = 2 * 3 + 4;
 
 // Scalars of the scheme, in lattice units, fixed for a run.
@@ -90,7 +94,8 @@ hipError_t launch_batch_step(int lattice, int storage, int bc, bool nts, const B
 hipError_t launch_clock_add(long long* clock, long long add, hipStream_t s);
 hipError_t launch_sum(const double* x, long long n, double* partials, int nblocks, double* out,
                       hipStream_t s);
-hipError_t launch_diag_finalize(const double* partials, int nblocks, double* out, hipStream_t s);
+hipError_t launch_diag_finalize(const double* partials, int nblocks, double* scratch, double* out,
+                                hipStream_t s);
 hipError_t launch_convert(const double* src, void* dst, int dst_dtype, long long n, double add,
                           double scale, hipStream_t s);
 

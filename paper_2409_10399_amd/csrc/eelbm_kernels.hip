@@ -208,23 +208,14 @@ __device__ __forceinline__ X* at(X* base, unsigned byte_off) {
     return reinterpret_cast<X*>(reinterpret_cast<char*>(base) + byte_off);
 }
 
-// reciprocal and square root of the compute type: the hardware's
-// single-instruction forms (1 ulp) in FP32, correctly rounded in FP64
+// reciprocal and square root of the compute type, correctly rounded
 template <class C>
 __device__ __forceinline__ C rcp(C v) {
     return C(1) / v;
 }
-template <>
-__device__ __forceinline__ float rcp<float>(float v) {
-    return __builtin_amdgcn_rcpf(v);
-}
 template <class C>
 __device__ __forceinline__ C root(C v) {
     return sqrt(v);
-}
-template <>
-__device__ __forceinline__ float root<float>(float v) {
-    return __builtin_amdgcn_sqrtf(v);
 }
 
 template <class C>
@@ -1051,6 +1042,45 @@ __global__ void __launch_bounds__(256) k_col_sum(const double* a, int nrows, int
     }
 }
 
+// Diagnostics finalize, first pass: workgroup g sums the rows
+// [g * chunk, (g + 1) * chunk) of the [nrows][kNDiag] block partials, each
+// thread a fixed subset of rows into registers (a row is 18 consecutive
+// doubles, so neighbouring threads read neighbouring rows), then a fixed
+// LDS tree per column.  Second pass: one workgroup sums the workgroup rows in
+// order.  The result depends only on nrows: bitwise reproducible.
+__global__ void __launch_bounds__(256) k_diag_rows(const double* a, int nrows, int chunk, double* out2) {
+    __shared__ double red[kNDiag][256];
+    const int r0 = blockIdx.x * chunk;
+    const int r1 = min(r0 + chunk, nrows);
+    double acc[kNDiag];
+#pragma unroll
+    for (int c = 0; c < kNDiag; ++c) acc[c] = 0.0;
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x) {
+        const double* row = a + (long long)r * kNDiag;
+#pragma unroll
+        for (int c = 0; c < kNDiag; ++c) acc[c] += row[c];
+    }
+#pragma unroll
+    for (int c = 0; c < kNDiag; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int c = 0; c < kNDiag; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < kNDiag) out2[(long long)blockIdx.x * kNDiag + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(64) k_diag_final(const double* out2, int g, double* out) {
+    if ((int)threadIdx.x < kNDiag) {
+        double v = 0.0;
+        for (int k = 0; k < g; ++k) v += out2[(long long)k * kNDiag + threadIdx.x];
+        out[threadIdx.x] = v;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_convert(const double* src, void* dst, int dtype, long long n, double add,
                                                  double scale) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
@@ -1177,8 +1207,15 @@ hipError_t launch_sum(const double* x, long long n, double* partials, int nblock
     return hipGetLastError();
 }
 
-hipError_t launch_diag_finalize(const double* partials, int nblocks, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(256), 0, s, partials, nblocks, kNDiag, out);
+hipError_t launch_diag_finalize(const double* partials, int nblocks, double* scratch, double* out, hipStream_t s) {
+    if (nblocks < 1) return hipErrorInvalidValue;
+    int g = (nblocks + kDiagRowsPerGroup - 1) / kDiagRowsPerGroup;
+    if (g > kDiagGroups) g = kDiagGroups;
+    const int chunk = (nblocks + g - 1) / g;
+    hipLaunchKernelGGL(k_diag_rows, dim3(g), dim3(256), 0, s, partials, nblocks, chunk, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, scratch, g, out);
     return hipGetLastError();
 }
 

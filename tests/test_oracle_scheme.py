@@ -501,3 +501,90 @@ def test_fp32_storage_floor_poiseuille():
     ex = exact("g")
     err = np.abs(prof - ex).max() / np.abs(ex).max()
     assert 1e-6 < err < 5e-6, err
+
+
+# ------------------------------------------- restart at t0 (reading R22)
+
+
+def test_restart_takes_the_lag_at_its_first_step():
+    """A run rebuilt from fields at a time t0 that is not a multiple of
+    n_gamma: with the Clift-Grace-Weber drag the lagged Lambda' of Eq. (137)
+    must be the one of the rebuilt state, or the drift-flux balance of
+    Eq. (124) is lost.  The uniform drift-flux state stays a fixed point when
+    restarted at t0 = 57 with n_gamma = 200, and the dashpot recurrence of
+    Eqs. (128), (131), (133) restarted at t0 = 2 with n_gamma = 3 refreshes at
+    t0 and then at t = 3, 6, ..."""
+    R, g, ag = 10.0, 1e-6 / 9.0, 0.2
+    al = 1.0 - ag
+    kappa = 9.667e-5
+    slip = math.sqrt((R - 1.0) * g / (kappa * (ag + al * R)))
+    cfg = cfg2(6, 8, rho_g=1.0, rho_l=R, g_hat=g, rho_ref="mixture_mean", drag="cgw", kappa_I=kappa,
+               gamma=1.0, n_gamma=200)
+    ul = (0.003, -0.002)
+    ug = (ul[0], ul[1] + slip)
+    o = Oracle(cfg, uniform_fields((8, 6), ag, ug, ul), t0=57)
+    o.step(30)
+    assert o.t == 87
+    r = o.read()
+    assert np.max(np.abs(r["u_g"][1] - ug[1])) < 1e-13
+    assert np.max(np.abs(r["u_l"][1] - ul[1])) < 1e-13
+    # without the drag (a zero Lambda') the gas accelerates by (R-1) g
+    # rho_l / rho_ref per step: the pin can fail
+    cfg0 = dict(cfg, kappa_I=0.0)
+    o0 = Oracle(cfg0, uniform_fields((8, 6), ag, ug, ul), t0=57)
+    o0.step(30)
+    assert np.max(np.abs(o0.read()["u_g"][1] - ug[1])) > 1e-6
+
+    Rr, gam, ng, t0 = 2.0, 1.0, 3, 2
+    cfg = cfg2(4, 4, rho_g=1.0, rho_l=Rr, gamma=gam, n_gamma=ng, sigma_grad=False)
+    ugv, ulv = np.array([0.02, 0.01]), np.array([0.01, -0.005])
+    dp = 1e-3
+    o = Oracle(cfg, uniform_fields((4, 4), 0.4, ugv, ulv, dp_k=dp), t0=t0)
+    eg = 1.0 + dp / CS2
+    ug_, ul_ = ugv.copy(), ulv.copy()
+    for t in range(t0, t0 + 12):
+        if t == t0 or t % ng == 0:
+            S2g = -gam * ug_ @ ug_ * (eg - 1.0)
+            S2l = -gam * ul_ @ ul_ * ((eg - 1.0) / Rr)
+        eg = eg + S2g
+        ug_, ul_ = ug_ * (1.0 + S2g), ul_ * (1.0 + S2l)
+        o.step()
+        m = o.moments()
+        assert abs(m["eps_g"][0, 0] - eg) < 1e-14
+        assert np.max(np.abs(m["u_g"][:, 0, 0] - ug_)) < 1e-15
+        assert np.max(np.abs(m["u_l"][:, 0, 0] - ul_)) < 1e-15
+
+
+# ------------------------------------------- Spalding map, Eq. (93) (R2)
+
+
+def test_spalding_B_on_every_branch():
+    """B(x) = x H(x) H(1 - x) + H(x - 1): 0 below 0, x on [0, 1], 1 above 1,
+    continuous at 0 and 1 with the half-maximum Heaviside (reading R2)."""
+    from oracle.scheme import spalding_B
+    x = np.array([-2.0, -1e-9, 0.0, 1e-9, 0.25, 0.5, 1.0 - 1e-12, 1.0, 1.0 + 1e-12, 3.0])
+    want = np.array([0.0, 0.0, 0.0, 1e-9, 0.25, 0.5, 1.0 - 1e-12, 1.0, 1.0, 1.0])
+    assert np.array_equal(spalding_B(x), want)
+
+
+@pytest.mark.parametrize("a_g,a_l,alpha_g", [
+    (0.3, 0.8, 0.3 / 1.1),     # both inside [0, 1]: a_g / (a_g + a_l)
+    (-0.1, 1.1, 0.0),          # a_g < 0, a_l > 1: B = 0 and 1
+    (1.2, -0.2, 1.0),          # a_g > 1, a_l < 0
+    (1.3, 0.5, 1.0 / 1.5),     # only a_g clipped
+    (-0.1, -0.2, 0.0),         # B(a_g) + B(a_l) = 0: the continuous phase fills (R2)
+    (0.0, 0.0, 0.0),
+])
+def test_spalding_renormalisation_of_the_raw_moments(a_g, a_l, alpha_g):
+    """The renormalised fractions of Eq. (93) from raw zeroth moments of f_ag,
+    f_al placed directly in the populations (rest populations of a uniform
+    state scaled to the wanted moment)."""
+    cfg = cfg2(3, 2, rho_l=2.0)
+    o = Oracle(cfg, uniform_fields((2, 3), 0.5, (0, 0), (0, 0)))
+    w = o.lat.w.reshape(-1, 1, 1)
+    o.f["ag"] = w * a_g * np.ones((1, 2, 3))
+    o.f["al"] = w * a_l * np.ones((1, 2, 3))
+    m = o.moments()
+    assert np.allclose(m["a_g"], a_g, rtol=0, atol=1e-15)
+    assert np.allclose(m["alpha_g"], alpha_g, rtol=0, atol=1e-15)
+    assert np.allclose(m["alpha_l"], 1.0 - alpha_g, rtol=0, atol=1e-15)
