@@ -28,6 +28,16 @@ Functions and what pins them (tests under ``tests/test_oracle_*.py``):
 * Boundary rules of Sec. 3.5 in several dimensions (walls, corners) --
   parity unpinned: the paper has no multi-dimensional boundary data; they are
   checked only for the 1D steady relations and for symmetry.
+* ``fd.FD`` -- a finite-difference method-of-lines solver of the same
+  two-fluid artificially compressible system (Sec. 3.4 in several dimensions,
+  classical Runge-Kutta in time), pinned by closed forms in
+  ``tests/test_oracle_fd.py`` (budgets, drift-flux fixed point, slip
+  relaxation, Taylor-Green decay, mixture sound speed, advected Gaussian,
+  weighted shear momentum); the LBM oracle approaches it at second order under
+  the diffusive refinement of Sec. 2.1.2 (16^2 / 32^2 / 64^2 boxes, all four
+  fields), which ties the coupled PDE content of ``scheme.Oracle.step`` --
+  sources, stress, volume-fraction force, drag, buoyancy together -- to an
+  independent discretisation.
 * ``mapping`` -- the similarity numbers printed for TEST #4 and the TEST #1
   outlet relations (``tests/golden/test4_mapping.json``,
   ``tests/golden/test1_outlet.json``).
