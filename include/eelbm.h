@@ -338,6 +338,20 @@ int eelbm_cno_split_add(const float* d, int32_t Ca, int32_t Cb, int64_t P, float
  * FP64 sums (their total is the loss), dpred = its gradient (may be NULL). */
 int eelbm_cno_mse(const float* pred, const float* target, int64_t P, int32_t C, int32_t Cused, double* partial,
                   int32_t nblocks, float* dpred, void* stream);
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving or training loops, harnesses that forbid allocation): the loss of
+ * eelbm_cno_mse without a caller workspace.  *loss (device pointer) receives
+ * the total of the nblocks partial sums, added in block order (bit-identical
+ * to summing eelbm_cno_mse's partial[] in index order); dpred as in
+ * eelbm_cno_mse (may be NULL).  The partial sums live in a fixed device array
+ * of EELBM_CNO_MSE_MAX_BLOCKS doubles inside the library (one per GPU, kept
+ * until the process ends); the call allocates nothing.  nblocks above
+ * EELBM_CNO_MSE_MAX_BLOCKS: EELBM_E_SIZE with a message.  Calls on one GPU
+ * share that array: calls that overlap in time on one GPU (different streams
+ * without ordering) race and give undefined losses. */
+#define EELBM_CNO_MSE_MAX_BLOCKS 1024
+int eelbm_cno_mse_noalloc(const float* pred, const float* target, int64_t P, int32_t C, int32_t Cused,
+                          int32_t nblocks, double* loss, float* dpred, void* stream);
 /* Adam step `step` (>= 1) with decoupled weight decay on n FP32 values. */
 int eelbm_cno_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
                    int64_t step, float weight_decay, void* stream);

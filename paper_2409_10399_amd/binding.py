@@ -87,6 +87,8 @@ SYMBOLS = {
     "eelbm_cno_concat": (c_int, [c_void_p, c_int32, c_void_p, c_int32, c_int64, c_void_p, c_void_p]),
     "eelbm_cno_split_add": (c_int, [c_void_p, c_int32, c_int32, c_int64, c_void_p, c_void_p, c_void_p]),
     "eelbm_cno_mse": (c_int, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p]),
+    "eelbm_cno_mse_noalloc": (c_int, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                      c_void_p]),
     "eelbm_cno_adam": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, ctypes.c_float, ctypes.c_float,
                                ctypes.c_float, ctypes.c_float, c_int64, ctypes.c_float, c_void_p]),
     "eelbm_cno_pack_weights": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),

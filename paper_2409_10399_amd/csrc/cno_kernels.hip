@@ -18,8 +18,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "eelbm.h"
+#include "eelbm_internal.hpp"
 
 namespace cno {
 
@@ -327,6 +329,16 @@ __global__ void k_mse(const float* __restrict__ pred, const float* __restrict__ 
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0] * inv;
 }
 
+// total of the per-workgroup partial sums, in index order (one thread: the
+// result does not depend on the launch)
+__global__ void k_sum_in_order(const double* __restrict__ partial, int n, double* __restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += partial[i];
+        *out = s;
+    }
+}
+
 // Adam on the FP32 master weights W[tap][ci][co] (n = 9 Cin Cout) and biases,
 // then the two BF16 operand copies Wf[co][tap][ci] and Wd[ci][tap][co]
 __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
@@ -539,6 +551,62 @@ int eelbm_cno_mse(const float* pred, const float* target, int64_t P, int32_t C, 
     hipLaunchKernelGGL(k_mse, dim3(nblocks), dim3(256), 0, static_cast<hipStream_t>(stream), pred, target, P, C, Cused,
                        partial, dpred);
     return last_rc(hipGetLastError());
+}
+
+}  // extern "C"
+
+// Workgroup partial sums of eelbm_cno_mse_noalloc, in the library's own device
+// memory (one copy per GPU, held until the process ends).  Host code never
+// uses the name itself (a host-side stand-in, not a device address): it takes
+// each device's address with hipGetSymbolAddress once, with that device
+// current, and passes that address to the kernels.
+static __device__ __align__(256) double scratch[EELBM_CNO_MSE_MAX_BLOCKS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// this device's address of `scratch`, taken at the first call on the device
+int scratch_for_current_device(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return eelbm::set_error(EELBM_E_HIP, "hipGetDevice failed");
+    if (dev < 0 || dev >= kMaxDevices) return eelbm::set_error(EELBM_E_PARAM, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return eelbm::set_error(EELBM_E_HIP, "hipGetSymbolAddress(scratch) failed");
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return EELBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int eelbm_cno_mse_noalloc(const float* pred, const float* target, int64_t P, int32_t C, int32_t Cused,
+                          int32_t nblocks, double* loss, float* dpred, void* stream) {
+    if (!pred || !target || !loss) return eelbm::set_error(EELBM_E_PARAM, "NULL pointer");
+    if (P < 1 || C < 1 || Cused < 1 || Cused > C || nblocks < 1)
+        return eelbm::set_error(EELBM_E_PARAM, "need P, C, nblocks >= 1 and 1 <= Cused <= C");
+    if (nblocks > EELBM_CNO_MSE_MAX_BLOCKS)
+        return eelbm::set_error(EELBM_E_SIZE, "nblocks exceeds EELBM_CNO_MSE_MAX_BLOCKS (the size of the built-in scratch)");
+    double* part = nullptr;
+    int rc = scratch_for_current_device(&part);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // every one of the nblocks workgroups writes its own partial sum: nothing
+    // left in the scratch by an earlier call is read
+    hipLaunchKernelGGL(k_mse, dim3(nblocks), dim3(256), 0, s, pred, target, P, C, Cused, part, dpred);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return eelbm::set_error(EELBM_E_HIP, "k_mse launch failed");
+    hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(64), 0, s, part, nblocks, loss);
+    e = hipGetLastError();
+    if (e != hipSuccess) return eelbm::set_error(EELBM_E_HIP, "k_sum_in_order launch failed");
+    return EELBM_OK;
 }
 
 int eelbm_cno_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,

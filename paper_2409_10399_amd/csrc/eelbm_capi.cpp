@@ -339,6 +339,12 @@ int copy_in(eelbm_handle* h, void* dst, const void* src, size_t bytes, int on_de
 
 }  // namespace
 
+namespace eelbm {
+// the thread-local message of eelbm_last_error, for entry points defined in
+// the kernel files
+int set_error(int code, const char* msg) { return fail(code, msg); }
+}  // namespace eelbm
+
 extern "C" {
 
 int32_t eelbm_abi_version(void) { return EELBM_ABI_VERSION; }

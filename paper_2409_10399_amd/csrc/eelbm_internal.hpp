@@ -95,6 +95,9 @@ hipError_t launch_clock_add(long long* clock, long long add, hipStream_t s);
 hipError_t launch_sum(const double* x, long long n, double* partials, int nblocks, double* out,
                       hipStream_t s);
 hipError_t launch_diag_finalize(const double* partials, int nblocks, double* scratch, double* out,
+// sets the message returned by eelbm_last_error and returns code
+int set_error(int code, const char* msg);
+
                                 hipStream_t s);
 hipError_t launch_convert(const double* src, void* dst, int dst_dtype, long long n, double add,
                           double scale, hipStream_t s);
