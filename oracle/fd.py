@@ -204,3 +204,4 @@ class FD:
     def read(self):
         return {"alpha_g": self.alpha_g.copy(), "u_g": self.u_g.copy(), "u_l": self.u_l.copy(),
                 "dp_k": self.dp.copy()}
+

@@ -376,8 +376,17 @@ class Oracle:
                 kind = p.bc[face]
                 fo = fstar[qs][idx]                          # f*(x_E, t, q*)
                 if s in ("bg", "bl"):
-                    # EQ(S), beta and c extrapolated full-way (Tables 1-2, reading R16).
-                    bB = self._face_values(m["b_" + phase], face, "fw", idx)
+                    # EQ(S), beta and c extrapolated full-way (Tables 1-2).
+                    # Reading R16: the beta extrapolated is the one the
+                    # equilibria of the source schemes carry, beta = 1 at the
+                    # start of every step at every node (text before
+                    # Eq. (105)), so the missing node emits f^eq(1, c_B).
+                    # (Extrapolating the post-streaming moment 1 - S instead
+                    # feeds S back into itself with gain 2 sum_q w_q at the
+                    # face: S grows about 1.5x per node towards an outlet and,
+                    # with the lag of Eq. (133), the tube of TEST #3 diverges
+                    # at t ~ 3.7e4.)
+                    bB = np.ones(k)
                     cB = self._face_values(m["c_" + phase], face, "fw", idx)
                     val = eq.feq_S(lat, bB, cB)[q]
                 elif kind == "inlet":

@@ -194,7 +194,7 @@ Layout layout(const eelbm_params& p, const Geometry& g) {
         return o;
     };
     const size_t n = (size_t)g.n;
-    const int NV = 2 * g.D + 4;
+    const int NV = 2 * g.D + 2;
     for (int k = 0; k < 2; ++k) L.pop[k] = take(pop_bytes(p, g));
     for (int k = 0; k < 2; ++k) L.cf[k] = take(cf_region_bytes(g));
     L.lag = take(lag_region_bytes(p, g));
@@ -626,7 +626,7 @@ void save_sizes(const eelbm_handle* h, SaveHeader* s) {
     s->pop_bytes = pop_bytes(h->p, h->g);
     s->cf_bytes = cf_region_bytes(h->g);
     s->lag_bytes = lag_region_bytes(h->p, h->g);
-    s->side_bytes = (size_t)2 * 2 * (2 * h->g.D + 4) * (size_t)h->g.face_n * h->g.csize;
+    s->side_bytes = (size_t)2 * 2 * (2 * h->g.D + 2) * (size_t)h->g.face_n * h->g.csize;
     s->macro_bytes = (size_t)(3 + 2 * h->g.D) * n * 8;
     s->part_bytes = (size_t)h->diag_blocks * kNDiag * 8;
     s->noise_bytes = (size_t)h->g.face_n * 8;

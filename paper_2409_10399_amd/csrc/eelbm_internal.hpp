@@ -12,7 +12,6 @@ constexpr int kNDiag = 18;  // per-node diagnostic sums (see k_step)
 // over at least kDiagRowsPerGroup block partials (scratch: kDiagGroups rows)
 constexpr int kDiagGroups = 256;
 constexpr int kDiagRowsPerGroup = 1024;
-constexpr int kMaxSideVals = 2 * 3 + 4;
 
 // Scalars of the scheme, in lattice units, fixed for a run.
 struct KParams {
@@ -95,10 +94,10 @@ hipError_t launch_clock_add(long long* clock, long long add, hipStream_t s);
 hipError_t launch_sum(const double* x, long long n, double* partials, int nblocks, double* out,
                       hipStream_t s);
 hipError_t launch_diag_finalize(const double* partials, int nblocks, double* scratch, double* out,
+                                hipStream_t s);
 // sets the message returned by eelbm_last_error and returns code
 int set_error(int code, const char* msg);
 
-                                hipStream_t s);
 hipError_t launch_convert(const double* src, void* dst, int dst_dtype, long long n, double add,
                           double scale, hipStream_t s);
 

@@ -25,7 +25,7 @@
 //  * the lag fields S''_g, S''_l (and Lambda' in 3D) when n_gamma > 1;
 //  * for the two node layers next to an inlet/outlet face, the macroscopic
 //    values the boundary extrapolations of Eqs. (160)-(161) need at the next
-//    step (u_g, u_l, alpha_g, alpha_l, S_g, S_l).
+//    step (u_g, u_l, alpha_g, alpha_l).
 //
 // The general gather computes every pulled node per lane (periodic wrap and
 // the boundary rules included).  In the periodic D3Q19 step with 16-bit
@@ -306,7 +306,7 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
     auto wall_hi = [&](int a) { return BC == kBcColumn ? int(a < D - 1) : p.wall_hi[a]; };
     const int face_lo = BC == kBcColumn ? int(EELBM_BC_INLET) : p.face_lo;
     const int face_hi = BC == kBcColumn ? int(EELBM_BC_OUTLET) : p.face_hi;
-    constexpr int NV = 2 * D + 4;  // side-buffer values per node
+    constexpr int NV = 2 * D + 2;  // side-buffer values per node: u_g, u_l, alpha_g, alpha_l
     constexpr int kBlk = 4 * Q * 64;  // population elements of one x-block
     const C third = C(1) / C(3);
     const long long plane_tiles = (long long)p.ntx * p.nty;
@@ -381,7 +381,11 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
         // values on the flow face (Sec. 3.5, STEP #1)
         C uinG[D], uinL[D], ain = C(0);                 // inlet: imposed u and alpha
         C ugB[D], ulB[D], agB = C(0), alB = C(0);       // outlet: EX(hw)
-        C cgB[D], clB[D], dbgB = C(0), dblB = C(0);     // beta, c: EX(fw); db = beta - 1
+        // f_b from beyond the face: EQ(S) with c extrapolated full-way and beta
+        // = 1, the value every node's equilibrium carries at the start of a
+        // step (beta is 1 before streaming, Eqs. (105)-(107)), so its
+        // extrapolation is 1 as well
+        C cgB[D], clB[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) uinG[a] = uinL[a] = ugB[a] = ulB[a] = cgB[a] = clB[a] = C(0);
         if constexpr (CH) {
@@ -430,9 +434,6 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                     }
                     agB = C(1.5) * ae - C(0.5) * an;
                     alB = p.renorm ? C(1) - agB : C(1.5) * ale - C(0.5) * aln;
-                    // beta - 1 = -S, extrapolated full-way
-                    dbgB = -(C(2) * sv(0, 2 * D + 2) - sv(1, 2 * D + 2));
-                    dblB = -(C(2) * sv(0, 2 * D + 3) - sv(1, 2 * D + 3));
                 }
             }
         }
@@ -637,8 +638,8 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                         usg += cgB[a] * cgB[a];
                         usl += clB[a] * clB[a];
                     }
-                    dbg = wq * (dbgB + (C(1) + dbgB) * poly2(dotc<L>(q, cgB), usg));
-                    dbl = wq * (dblB + (C(1) + dblB) * poly2(dotc<L>(q, clB), usl));
+                    dbg = wq * poly2(dotc<L>(q, cgB), usg);
+                    dbl = wq * poly2(dotc<L>(q, clB), usl);
                 } else {
                     const int xs = wrap_axis(x - L::c[q][0], p.nx, per(0));
                     const int ys = wrap_axis(y - L::c[q][1], p.ny, per(1));
@@ -914,8 +915,6 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                     }
                     put(2 * D, alg);
                     put(2 * D + 1, all);
-                    put(2 * D + 2, Sg);
-                    put(2 * D + 3, Sl);
                 }
             }
         }
