@@ -77,6 +77,9 @@ class Params:
         self.n_ramp = float(cfg.get("n_ramp", 0.0))
         self.renormalize = bool(cfg.get("renormalize", True))
         self.sigma_grad = bool(cfg.get("sigma_grad", True))
+        # test switch: the slope limiter of reading R13 (always on in the
+        # library; off only to show what it prevents)
+        self.grad_limiter = bool(cfg.get("grad_limiter", True))
 
 
 class Oracle:
@@ -238,8 +241,20 @@ class Oracle:
         b_l = (self.rho_ref / p.rho_l - 1.0) * p.g_hat
 
         # Forces, Eqs. (24) and (26) with F_lg = -F_gl and F_g = 0.
-        sgrad_g = np.einsum("cd...,d...->c...", sig_g, grad_g) / ag_f
-        sgrad_l = np.einsum("cd...,d...->c...", sig_l, grad_l) / al_f
+        # Reading R13 (continued): in sigma . grad(alpha) / alpha the
+        # gradient is limited to |grad alpha_phi| <= max(alpha_phi, alpha_min)
+        # per lattice spacing -- a slope limiter, as the paper proposes for
+        # this term where alpha -> 0 (Sec. 2.1): a log-gradient steeper than
+        # one per node is not resolved, and at nodes the clamp of Eq. (93)
+        # has emptied of a phase the raw flux-based gradient of Eq. (91)
+        # would otherwise be divided by alpha_min.
+        gnorm = np.sqrt(np.sum(grad_g * grad_g, axis=0))          # |grad alpha_l| = |grad alpha_g|
+        lim_g = np.where(gnorm > ag_f, ag_f / np.where(gnorm > 0, gnorm, 1.0), 1.0)
+        lim_l = np.where(gnorm > al_f, al_f / np.where(gnorm > 0, gnorm, 1.0), 1.0)
+        if not p.grad_limiter:
+            lim_g = lim_l = 1.0
+        sgrad_g = np.einsum("cd...,d...->c...", sig_g, grad_g * lim_g) / ag_f
+        sgrad_l = np.einsum("cd...,d...->c...", sig_l, grad_l * lim_l) / al_f
         if not p.sigma_grad:
             sgrad_g = np.zeros_like(sgrad_g)
             sgrad_l = np.zeros_like(sgrad_l)

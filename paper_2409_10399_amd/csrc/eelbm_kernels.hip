@@ -810,6 +810,22 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
         const C K = p.cgw ? C(p.kappa_I) * Laml : C(p.K_I);
         C Gg[D], Gl[D];
         const C inv_agf = rcp(agf), inv_alf = rcp(alf), inv_alfR = inv_alf * invR;
+        // slope limiter of sigma . grad(alpha) / alpha: |grad alpha_phi| is
+        // capped at max(alpha_phi, alpha_min) per lattice spacing (a steeper
+        // log-gradient is not resolved, and where the clamp of Eq. (93) has
+        // emptied a phase the flux-based gradient would meet alpha_min), so
+        // the factor grad / alpha becomes grad / |grad| there
+        C kgg = inv_agf, kgl = inv_alf;
+        if (p.sigma_grad) {
+            C g2 = C(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) g2 += grad[a] * grad[a];
+            if (g2 > agf * agf || g2 > alf * alf) {
+                const C ig = rcp(root(g2));
+                if (g2 > agf * agf) kgg = ig;
+                if (g2 > alf * alf) kgl = ig;
+            }
+        }
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             C sgg = C(0), sgl = C(0);
@@ -819,8 +835,8 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                     sgg += sg[sym<D>(a, bb)] * grad[bb];
                     sgl -= sl[sym<D>(a, bb)] * grad[bb];
                 }
-                sgg = sgg * inv_agf;
-                sgl = sgl * inv_alf;
+                sgg = sgg * kgg;
+                sgl = sgl * kgl;
             }
             const C bg = a == p.up ? C(p.b_g) : C(0);
             const C bl = a == p.up ? C(p.b_l) : C(0);

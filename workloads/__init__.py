@@ -190,10 +190,11 @@ def blob_field_3d(n, nblobs, seed=0, peak=0.3, rmin=4.0, rmax=12.0, cut=4.0, bac
     return np.clip(background + field, 0.0, peak)
 
 
-def column_3d(n=256, nblobs=256, seed=0, background=0.01):
+def column_3d(n=256, nblobs=256, seed=0, background=0.0):
     """D3Q19 periodic column, up = +z, R = 1000, Clift-Grace-Weber drag for
-    3 mm bubbles, seeded Gaussian gas blobs on a background gas fraction (the
-    scheme divides by alpha_g, so no node is gas-free), both phases at rest."""
+    3 mm bubbles, seeded Gaussian gas blobs (truncated at 4 radii, so most of
+    the box is gas-free), both phases at rest; `background` adds a uniform
+    gas fraction under the blobs."""
     alpha = blob_field_3d(n, nblobs, seed, background=background)
     cfg = _base("D3Q19", nx=n, ny=n, nz=n, rho_g=1.0, rho_l=1000.0, drag="cgw",
                 kappa_I=KAPPA_HAT_3MM, g_hat=G_HAT_R1000, up_axis=2, rho_ref="mixture_mean",
