@@ -29,13 +29,15 @@ SURROGATE_SUMMARY = os.path.join(ROOT, "profiles", "surrogate_speedup_channel256
 
 
 def algorithmic_bytes_per_node(D, Q, tbytes, cbytes, lag):
-    """State one node-update must read and write: 4Q post-collision
-    populations (f_g, f_l, f_ag, f_al) read and written, the 1 + D
-    imposed-velocity values (alpha_g, u_g - u_l) that stand in for the 2Q
-    source-scheme populations read and written, and the 3 lag values
+    """State the method must carry from one node-update to the next: 4Q
+    post-collision populations (f_g, f_l, f_ag, f_al) read and written, the
+    1 + D imposed-velocity values (alpha_g, u_g - u_l) that stand in for the
+    2Q source-scheme populations read and written, and the 3 lag values
     (S''_g, S''_l, Lambda') read; their write every n_gamma steps is not
-    counted.  D2Q9 FP32: 288 + 24 + 12 = 324 B.  (The kernel moves 328 B:
-    its 16-byte record also rewrites Lambda' every step.)"""
+    counted.  D2Q9 FP32: 288 + 24 + 12 = 324 B.  The kernel moves more than
+    this minimum: its record also carries u_g, u_l and eps_g - 1 as the
+    reference of the stored residuals (D2Q9 FP32: 360 B per node-update);
+    that overhead of the storage format counts against the kernel."""
     return 2 * 4 * Q * tbytes + 2 * (1 + D) * cbytes + (3 * cbytes if lag else 0)
 
 

@@ -57,19 +57,38 @@ int env_int(const char* name, int dflt) {
     return v && *v ? std::atoi(v) : dflt;
 }
 
+// LDS of a tile's staged record window (FP32 compute): 32 bytes for each
+// node of the tile and its one-node halo, in three planes in D3Q19; the
+// window must fit the 64 KiB a workgroup can address.
+constexpr size_t kMaxWindowBytes = 65536;
+size_t window_bytes(const eelbm_params& p, int bx, int by) {
+    if (p.storage == EELBM_FP64) return 0;
+    return (size_t)(bx + 2) * (by + 2) * (p.lattice == EELBM_D3Q19 ? 3 : 1) * 32;
+}
+bool tile_ok(const eelbm_params& p, int bx, int by) {
+    return bx >= 64 && by >= 1 && bx % 64 == 0 && bx * by <= 256 && window_bytes(p, bx, by) <= kMaxWindowBytes;
+}
+
 // Launch shape: tiles of bx * by nodes (a whole number of 64-wide wavefronts,
 // at most 256 threads), one workgroup per tile, tiles of all planes in one
-// grid dimension.  bx = 0 picks the default: rows of up to 256 nodes.
-// EELBM_TILE_X / EELBM_TILE_Y / EELBM_XCD_REMAP override the default.
+// grid dimension.  bx = 0 picks the default: rows of up to 256 nodes in
+// D2Q9, 64 x 4 tiles in D3Q19 (whose record window of a 256-node row would
+// not fit the workgroup's LDS).  EELBM_TILE_X / EELBM_TILE_Y /
+// EELBM_XCD_REMAP override the default.
 void set_tiles(const eelbm_params& p, Geometry* g, int bx, int by, int xcd) {
     if (bx <= 0) {
         bx = env_int("EELBM_TILE_X", 0);
         by = env_int("EELBM_TILE_Y", 0);
     }
-    if (bx <= 0 || by <= 0 || bx % 64 != 0 || bx * by > 256) {
-        bx = ((p.nx + 63) / 64) * 64;
-        if (bx > 256) bx = 256;
-        by = 1;
+    if (!tile_ok(p, bx, by)) {
+        if (p.lattice == EELBM_D3Q19) {
+            bx = 64;
+            by = 4;
+        } else {
+            bx = ((p.nx + 63) / 64) * 64;
+            if (bx > 256) bx = 256;
+            by = 1;
+        }
     }
     if (xcd < 0) xcd = env_int("EELBM_XCD_REMAP", 1);
     g->block = dim3(bx, by, 1);
@@ -93,9 +112,9 @@ int validate(const eelbm_params* pp, Geometry* g) {
     if (D == 2 && p.nz != 1) return fail(EELBM_E_PARAM, "D2Q9 needs nz = 1");
     if (p.ny > 65535 || p.nz > 65535) return fail(EELBM_E_PARAM, "ny and nz must be <= 65535");
     const long long n = (long long)p.nx * p.ny * p.nz;
-    // every per-node array (the widest: 4-wide FP64 records) stays below 4 GiB,
+    // every per-node array (the widest: 8-wide FP64 records) stays below 4 GiB,
     // so kernels address it with 32-bit byte offsets
-    if ((unsigned long long)n * 4 * (p.storage == EELBM_FP64 ? 8 : 4) >= (1ull << 32))
+    if ((unsigned long long)n * 8 * (p.storage == EELBM_FP64 ? 8 : 4) >= (1ull << 32))
         return fail(EELBM_E_PARAM, "too many nodes for one lattice");
     // ... and so does one z-plane of a population copy (buffer descriptors)
     {
@@ -176,7 +195,7 @@ constexpr size_t kLastLevelCacheBytes = 256ull << 20;
 
 // imposed-velocity region of one ping-pong copy: [n] 4-wide records, then
 // [n] alpha_l values (used only without renormalisation)
-size_t cf_records_bytes(const Geometry& g) { return align256(4 * (size_t)g.n * g.csize); }
+size_t cf_records_bytes(const Geometry& g) { return align256(8 * (size_t)g.n * g.csize); }
 size_t cf_region_bytes(const Geometry& g) { return cf_records_bytes(g) + (size_t)g.n * g.csize; }
 // lag region: [n] 2-wide records (S''_g, S''_l), then [n] Lambda' in 3D
 size_t lag_records_bytes(const Geometry& g) { return align256(2 * (size_t)g.n * g.csize); }
@@ -307,6 +326,15 @@ void fill_kparams(eelbm_handle* h) {
     k.ul_in_min = p.ul_in_min;
     k.n_ramp = p.n_ramp;
     k.alpha_ref = h->alpha_ref;
+    // FP16 scales of the stored residuals (only used with FP16 storage): 2^20
+    // for f_g, f_ag, f_al, 2^20 * 2^round(log2 min(R, 64)) for the moving
+    // populations of f_l (its rest population is stored unscaled)
+    const double R = p.rho_l / p.rho_g;
+    int e = (int)std::lround(std::log2(std::min(std::max(R, 1.0), 64.0)));
+    k.h16_up[0] = std::ldexp(1.0f, 20);
+    k.h16_up[1] = std::ldexp(1.0f, 20 + e);
+    k.h16_down[0] = std::ldexp(1.0f, -20);
+    k.h16_down[1] = std::ldexp(1.0f, -(20 + e));
 }
 
 int launch(eelbm_handle* h, bool init, int64_t t, bool last) {
@@ -508,6 +536,8 @@ int eelbm_set_launch(eelbm_handle* h, int32_t tile_x, int32_t tile_y, int32_t xc
     if (!h) return fail(EELBM_E_PARAM, "handle is NULL");
     if (tile_x < 64 || tile_y < 1 || tile_x % 64 != 0 || tile_x * tile_y > 256)
         return fail(EELBM_E_PARAM, "tile_x must be a multiple of 64 (one x-block per wavefront), at most 256 nodes");
+    if (!tile_ok(h->p, tile_x, tile_y))
+        return fail(EELBM_E_PARAM, "the tile's record window exceeds 64 KiB of LDS (D3Q19: at most 64x4 or 128x2)");
     if (h->g.D == 2 && tile_y > h->p.ny) return fail(EELBM_E_PARAM, "tile_y exceeds ny");
     set_tiles(h->p, &h->g, tile_x, tile_y, xcd_remap ? 1 : 0);
     fill_kparams(h);
@@ -786,6 +816,8 @@ int check_members(eelbm_handle* const* m, int32_t n, int32_t tx, int32_t ty) {
         for (int32_t j = 0; j < i; ++j)
             if (m[j] == h) return fail(EELBM_E_PARAM, "a lattice appears twice in the batch");
     }
+    if (!tile_ok(m[0]->p, tx, ty))
+        return fail(EELBM_E_PARAM, "the tile's record window exceeds 64 KiB of LDS (D3Q19: at most 64x4 or 128x2)");
     return EELBM_OK;
 }
 
@@ -1029,6 +1061,7 @@ int eelbm_autotune(eelbm_handle* h, int32_t steps, int32_t force, int32_t* tile_
     for (int bx = 64; bx <= bx_max; bx += 64) {
         for (int by = 1; bx * by <= 256; by *= 2) {
             if (by > h->p.ny) break;
+            if (!tile_ok(h->p, bx, by)) continue;
             for (int xcd = 0; xcd < 2; ++xcd) {
                 set_tiles(h->p, &h->g, bx, by, xcd);
                 fill_kparams(h);

@@ -40,14 +40,15 @@ struct KParams {
     double alpha_ref;   // reference of the f_alpha deviations (mean initial alpha_g)
     long long n_gamma;  // lag refresh period
     double a_in_max, a_in_min, ug_in_max, ug_in_min, ul_in_max, ul_in_min, n_ramp;  // inlet ramp, Eq. (153)
+    float h16_up[2], h16_down[2];  // FP16 storage scales: [0] f_g, f_ag, f_al; [1] moving f_l
 };
 
 // Device pointers of one launch (ping-pong halves already selected).
 struct KBuffers {
     const void* pop_in;   // [4][Q][n] storage type: deviations of f_g, f_l, f_ag, f_al
     void* pop_out;
-    const void* cf_in;    // [n] records of 4 compute-type values: alpha_g, du(D) = u_g - u_l,
-    void* cf_out;         //     and Lambda' in the fourth slot of D2Q9
+    const void* cf_in;    // [n] records of 8 compute-type values: alpha_g, u_g(D), u_l(D),
+    void* cf_out;         //     Lambda' (D2Q9), eps_g - 1
     const void* al_in;    // [n] alpha_l (read and written only without renormalisation)
     void* al_out;
     void* lag;            // [n] records of 2: S''_g, S''_l

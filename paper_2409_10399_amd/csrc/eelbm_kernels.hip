@@ -13,26 +13,21 @@
 // pop_in_plane).
 //
 // State kept between launches, per node:
-//  * f_g, f_l as deviations from w_q, f_ag, f_al as deviations from
-//    w_q alpha_r and w_q (1 - alpha_r) (alpha_r: the mean initial gas
-//    fraction), post-collision, in the storage type;
-//  * one 4-wide record (alpha_g, u_g - u_l, and Lambda' in the free slot of
-//    D2Q9): the post-collision f_b of the lattice kinetic scheme is the pure
-//    function f^eq(1, c_phi) of alpha_g and u_g - u_l (Eqs. (95), (97) with
-//    beta = 1), so f_b is rebuilt at the gather from the upstream node's
-//    record instead of being stored -- 1 + D numbers instead of 2Q, read
-//    with one 16-byte load per upstream node;
+//  * f_g, f_l, f_ag, f_al, post-collision, in the storage type, as residuals
+//    against the equilibrium part of their sender's record (see Rec8);
+//  * one 8-wide record (alpha_g - alpha_r, u_g, u_l, eps_g - 1, and Lambda'
+//    in D2Q9), the reference of those residuals; the post-collision f_b of
+//    the lattice kinetic scheme is the pure function f^eq(1, c_phi) of
+//    alpha_g and u_g - u_l (Eqs. (95), (97) with beta = 1), so f_b is rebuilt
+//    at the gather from the upstream node's record instead of being stored;
 //  * the lag fields S''_g, S''_l (and Lambda' in 3D) when n_gamma > 1;
 //  * for the two node layers next to an inlet/outlet face, the macroscopic
 //    values the boundary extrapolations of Eqs. (160)-(161) need at the next
 //    step (u_g, u_l, alpha_g, alpha_l).
 //
-// The general gather computes every pulled node per lane (periodic wrap and
-// the boundary rules included).  In the periodic D3Q19 step with 16-bit
-// storage, wavefronts whose nodes all pull from interior neighbours take an
-// interior gather instead (a wave-uniform base plus one shared 32-bit offset
-// per x-shift); elsewhere that second gather costs more in registers than it
-// saves.
+// Every node computes its pulls per lane (periodic wrap and the boundary
+// rules included).  In FP32 compute the upstream records of a tile are staged
+// in LDS first (one coalesced load per record of the tile and its halo).
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -47,6 +42,7 @@ namespace eelbm {
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
@@ -67,37 +63,145 @@ struct Compute<double> {
     using C = double;
 };
 
-// 4-wide imposed-velocity record and 2-wide lag record (one vector load each)
+// Per-node record of 8 compute-type values written by every step (two
+// 16-byte vectors in FP32): alpha_g - a_r (renormalised alpha_g as a
+// deviation from the reference gas fraction a_r, so that carrying it from step
+// to step rounds at the scale of the deviation), u_g, u_l and the gas
+// density deviation eps_g - 1 of the node's collision, plus Lambda' (the
+// lagged Clift-Grace-Weber factor) in D2Q9.  It serves two purposes:
+//  * the post-collision f_b of the lattice kinetic scheme is the pure
+//    function f^eq(1, c_phi) of alpha_g and u_g - u_l (Eqs. (95), (97) with
+//    beta = 1), so f_b is rebuilt at the gather from the upstream record
+//    instead of being stored;
+//  * populations are stored relative to the equilibrium part E_q(r) of their
+//    sender's record r:
+//        f_g:  w_q (de + 3 v_q.u_g)            f_l:  w_q 3 v_q.u_l
+//        f_ag: w_q (da + 3 a v_q.u_g)          f_al: w_q (-da + 3 (1 - a) v_q.u_l)
+//    (deviations; da = alpha_g - a_r from the record, a = a_r + da), so what is
+//    stored is the non-equilibrium and second-order part only: in FP32 the
+//    rounding no longer scales with the velocity, and 16-bit types keep
+//    their precision for the small fields (the pressure deviation, the
+//    liquid at large density ratios).  The receiver adds E of the sender's
+//    record back; any rounding of the record is the same on both sides.
+template <int D>
+constexpr int kDe = 1 + 2 * D;  // slot of eps_g - 1
+constexpr int kLam = 6;         // slot of Lambda' (D2Q9; read by the node itself only)
 template <class C>
-struct alignas(4 * sizeof(C)) Rec4 {
-    C v[4];
+struct alignas(8 * sizeof(C)) Rec8 {
+    C v[8];
 };
 template <class C>
 struct alignas(2 * sizeof(C)) Rec2 {
     C v[2];
 };
 
-__device__ __forceinline__ Rec4<float> ld_rec(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float) {
-    return __builtin_bit_cast(Rec4<float>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
-}
-__device__ __forceinline__ Rec4<double> ld_rec(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double) {
+__device__ __forceinline__ Rec8<float> ld_rec8(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float) {
     struct Two {
         u32x4 a, b;
     } t;
     t.a = __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0);
     t.b = __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)(so + 16), 0);
-    return __builtin_bit_cast(Rec4<double>, t);
+    return __builtin_bit_cast(Rec8<float>, t);
 }
-__device__ __forceinline__ void st_rec(__amdgpu_buffer_rsrc_t r, unsigned vo, const Rec4<float>& v) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)vo, 0, 0);
+__device__ __forceinline__ Rec8<double> ld_rec8(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double) {
+    struct Four {
+        u32x4 a, b, c, d;
+    } t;
+    t.a = __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0);
+    t.b = __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)(so + 16), 0);
+    t.c = __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)(so + 32), 0);
+    t.d = __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)(so + 48), 0);
+    return __builtin_bit_cast(Rec8<double>, t);
 }
-__device__ __forceinline__ void st_rec(__amdgpu_buffer_rsrc_t r, unsigned vo, const Rec4<double>& v) {
+// the part of an upstream node's record the gather uses: all 8 slots in
+// D3Q19, slots 0-5 in D2Q9 (one 16-byte and one 8-byte load in FP32)
+template <int D>
+__device__ __forceinline__ Rec8<float> ld_rec_up(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float c) {
+    if constexpr (D == 3) {
+        return ld_rec8(r, vo, so, c);
+    } else {
+        const f32x4 a = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+        const f32x2 bq = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)(so + 16), 0));
+        Rec8<float> o;
+        o.v[0] = a.x;
+        o.v[1] = a.y;
+        o.v[2] = a.z;
+        o.v[3] = a.w;
+        o.v[4] = bq.x;
+        o.v[5] = bq.y;
+        o.v[6] = 0.0f;
+        o.v[7] = 0.0f;
+        return o;
+    }
+}
+template <int D>
+__device__ __forceinline__ Rec8<double> ld_rec_up(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double c) {
+    if constexpr (D == 3) {
+        return ld_rec8(r, vo, so, c);
+    } else {
+        Rec8<double> o;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const f64x2 v =
+                __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)(so + 16 * k), 0));
+            o.v[2 * k] = v.x;
+            o.v[2 * k + 1] = v.y;
+        }
+        o.v[6] = 0.0;
+        o.v[7] = 0.0;
+        return o;
+    }
+}
+__device__ __forceinline__ void st_rec8(__amdgpu_buffer_rsrc_t r, unsigned vo, const Rec8<float>& v) {
     struct Two {
         u32x4 a, b;
     };
     const Two t = __builtin_bit_cast(Two, v);
     __builtin_amdgcn_raw_buffer_store_b128(t.a, r, (int)vo, 0, 0);
     __builtin_amdgcn_raw_buffer_store_b128(t.b, r, (int)vo, 16, 0);
+}
+__device__ __forceinline__ void st_rec8(__amdgpu_buffer_rsrc_t r, unsigned vo, const Rec8<double>& v) {
+    struct Four {
+        u32x4 a, b, c, d;
+    };
+    const Four t = __builtin_bit_cast(Four, v);
+    __builtin_amdgcn_raw_buffer_store_b128(t.a, r, (int)vo, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(t.b, r, (int)vo, 16, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(t.c, r, (int)vo, 32, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(t.d, r, (int)vo, 48, 0);
+}
+
+// Upstream records staged in LDS (FP32 compute): one 32-byte slot per node
+// of the tile and its one-node halo; D2Q9 uses slots 0-5 of it.
+extern __shared__ Rec8<float> lds_win[];
+
+template <int D>
+__device__ __forceinline__ void lds_put(Rec8<float>* d, const Rec8<float>& r) {
+    if constexpr (D == 3) {
+        *d = r;
+    } else {
+        *reinterpret_cast<f32x4*>(d->v) = f32x4{r.v[0], r.v[1], r.v[2], r.v[3]};
+        *reinterpret_cast<f32x2*>(d->v + 4) = f32x2{r.v[4], r.v[5]};
+    }
+}
+template <int D>
+__device__ __forceinline__ Rec8<float> lds_get(const Rec8<float>* d) {
+    if constexpr (D == 3) {
+        return *d;
+    } else {
+        const f32x4 a = *reinterpret_cast<const f32x4*>(d->v);
+        const f32x2 c = *reinterpret_cast<const f32x2*>(d->v + 4);
+        Rec8<float> o;
+        o.v[0] = a.x;
+        o.v[1] = a.y;
+        o.v[2] = a.z;
+        o.v[3] = a.w;
+        o.v[4] = c.x;
+        o.v[5] = c.y;
+        o.v[6] = 0.0f;
+        o.v[7] = 0.0f;
+        return o;
+    }
 }
 
 // ------------------------------------------------- buffer-instruction I/O
@@ -123,7 +227,8 @@ struct Pop4;
 // vector element is not reliable with this compiler.)
 template <>
 struct Pop4<float> {
-    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float* o) {
+    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float* o,
+                                              const KParams&, bool) {
         const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, kNT));
         o[0] = v.x;
         o[1] = v.y;
@@ -131,14 +236,16 @@ struct Pop4<float> {
         o[3] = v.w;
     }
     template <int POL>
-    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const float* v) {
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const float* v,
+                                              const KParams&, bool) {
         const f32x4 w = {v[0], v[1], v[2], v[3]};
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, w), r, (int)vo, (int)so, POL);
     }
 };
 template <>
 struct Pop4<double> {
-    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double* o) {
+    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double* o,
+                                              const KParams&, bool) {
         const f64x2 a = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, kNT));
         const f64x2 b =
             __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)(so + 16), kNT));
@@ -148,46 +255,54 @@ struct Pop4<double> {
         o[3] = b.y;
     }
     template <int POL>
-    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const double* v) {
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const double* v,
+                                              const KParams&, bool) {
         const f64x2 a = {v[0], v[1]}, b = {v[2], v[3]};
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, a), r, (int)vo, (int)so, POL);
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, b), r, (int)vo, (int)(so + 16), POL);
     }
 };
-// 16-bit storage: set k sits in half-word k of the 8-byte group.  FP16 holds
-// the deviations multiplied by 2^15 (exact): every deviation of magnitude in
-// [2e-9, 2) is then a normal FP16 number with relative precision 2^-11 --
-// unscaled, the liquid deviations at R = 1000 (~1e-6) would be subnormal, with
-// an absolute resolution of 6e-8.  BF16 has the exponent range of FP32 and is
-// stored unscaled.
+// 16-bit storage: set k sits in half-word k of the 8-byte group.  The stored
+// residuals (non-equilibrium and second-order parts, see Rec8) are small, so
+// FP16 holds them multiplied by a power of two per set (KParams::h16_up,
+// exact): 2^20 for f_g, f_ag, f_al (residuals in [6e-11, 0.06) are normal FP16
+// numbers with relative precision 2^-11) and 2^20 min(R, 64) for the moving
+// populations of f_l, whose residuals shrink with the density ratio.  The
+// rest population of f_l is stored unscaled: it carries the liquid density
+// deviation sum f_l - 1, which no other quantity of the step uses (the liquid
+// feels the pressure through Eq. (32) instead) and which drifts freely where
+// liquid piles up -- at the inlet corners of the channel it passes 0.06, the
+// largest residual FP16 holds at the 2^20 scale, within 4000 steps.  BF16 has the exponent range of
+// FP32 and is stored unscaled.
 template <class H>
 struct Pop4Half {
     static constexpr bool kHalf = std::is_same<H, __half>::value;
-    static constexpr float kUp = kHalf ? 32768.0f : 1.0f, kDown = kHalf ? 1.0f / 32768.0f : 1.0f;
-    static __device__ __forceinline__ float to_f(unsigned short h) {
+    static __device__ __forceinline__ float to_f(unsigned short h, float down) {
         if constexpr (kHalf)
-            return __half2float(__ushort_as_half(h)) * kDown;
+            return __half2float(__ushort_as_half(h)) * down;
         else
             return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, h));
     }
-    static __device__ __forceinline__ unsigned short from_f(float v) {
+    static __device__ __forceinline__ unsigned short from_f(float v, float up) {
         if constexpr (kHalf)
-            return __half_as_ushort(__float2half_rn(v * kUp));
+            return __half_as_ushort(__float2half_rn(v * up));
         else
             return __builtin_bit_cast(unsigned short, __float2bfloat16(v));
     }
-    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float* o) {
+    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float* o,
+                                              const KParams& p, bool rest) {
         const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, kNT);
-        o[0] = to_f((unsigned short)(v.x & 0xffffu));
-        o[1] = to_f((unsigned short)(v.x >> 16));
-        o[2] = to_f((unsigned short)(v.y & 0xffffu));
-        o[3] = to_f((unsigned short)(v.y >> 16));
+        o[0] = to_f((unsigned short)(v.x & 0xffffu), p.h16_down[0]);
+        o[1] = to_f((unsigned short)(v.x >> 16), rest ? 1.0f : p.h16_down[1]);
+        o[2] = to_f((unsigned short)(v.y & 0xffffu), p.h16_down[0]);
+        o[3] = to_f((unsigned short)(v.y >> 16), p.h16_down[0]);
     }
     template <int POL>
-    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const float* v) {
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const float* v,
+                                              const KParams& p, bool rest) {
         u32x2 w;
-        w.x = (unsigned)from_f(v[0]) | ((unsigned)from_f(v[1]) << 16);
-        w.y = (unsigned)from_f(v[2]) | ((unsigned)from_f(v[3]) << 16);
+        w.x = (unsigned)from_f(v[0], p.h16_up[0]) | ((unsigned)from_f(v[1], rest ? 1.0f : p.h16_up[1]) << 16);
+        w.y = (unsigned)from_f(v[2], p.h16_up[0]) | ((unsigned)from_f(v[3], p.h16_up[0]) << 16);
         __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)vo, (int)so, POL);
     }
 };
@@ -247,19 +362,149 @@ __device__ __forceinline__ int wrap_axis(int v, int nax, int per) {
     return v;
 }
 
-// source-scheme population deviations of one upstream node: w_q-normalised
-// f^eq(1, c) - w_q with c_g = alpha_l du, c_l = -alpha_g du (Eqs. (72), (97))
+// Source-scheme populations entering a node (Eqs. (72), (95), (97)), as
+// deviations f_b - w_q - w_q P_q(c_0) from the node's own equilibrium part,
+// P_q(c) = 3 v_q.c + 9/2 (v_q.c)^2 - 3/2 |c|^2, with c_0 the node's own
+// imposed velocity (c_g = alpha_l du, c_l = -alpha_g du, du = u_g - u_l).
+// sum_q w_q P_q(c_0) = 0, so the sources S = 1 - sum f_b are unchanged, and
+// for a sender with imposed velocity c_s
+//   P_q(c_s) - P_q(c_0) = 3 v.d + 9/2 (v.d)(v.(c_s + c_0)) - 3/2 d.(c_s + c_0)
+// with d = c_s - c_0: every term carries the difference d, formed from the
+// differences of the two records (dals = alpha_l,s - alpha_l,0, da =
+// alpha_g,s - alpha_g,0, ddu = (u_g,s - u_g,0) - (u_l,s - u_l,0), each exact
+// in the record's type), so the sum keeps the precision of the small source
+// instead of cancelling terms of the size of c or |c|^2.
 template <class L, class C>
-__device__ __forceinline__ void beta_dev(int q, C as, C als, const C* du, C& dbg, C& dbl) {
-    constexpr int D = L::D;
-    C vd = C(0), dd = C(0);
+__device__ __forceinline__ C p_diff(int q, const C* d, const C* s) {
+    C ds = C(0);
 #pragma unroll
-    for (int a = 0; a < D; ++a) dd += du[a] * du[a];
-    vd = dotc<L>(q, du);
-    const C even = C(4.5) * vd * vd - C(1.5) * dd;
+    for (int a = 0; a < L::D; ++a) ds += d[a] * s[a];
+    const C vd = dotc<L>(q, d);
+    return C(L::w[q]) * (C(3) * vd + C(4.5) * vd * dotc<L>(q, s) - C(1.5) * ds);
+}
+template <class L, class C>
+__device__ __forceinline__ void beta_rel(int q, C as, C als, const C* dus, C dals, C da, C al0, C a0, const C* ddu,
+                                         C& dbg, C& dbl) {
+    constexpr int D = L::D;
+    C sg[D], sl[D], dcg[D], dcl[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        dcg[a] = dals * dus[a] + al0 * ddu[a];
+        dcl[a] = -(da * dus[a] + a0 * ddu[a]);
+        sg[a] = C(2) * (als * dus[a]) - dcg[a];  // c_s + c_0
+        sl[a] = C(-2) * (as * dus[a]) - dcl[a];
+    }
+    dbg = p_diff<L>(q, dcg, sg);
+    dbl = p_diff<L>(q, dcl, sl);
+}
+
+// f_b entering through an inlet/outlet face: EQ(S) with beta = 1 and the
+// imposed velocity extrapolated full-way (Tables 1-2, beta read as the 1 the
+// equilibria carry); through a wall: EQ(S)(1, 0) -- both as deviations from
+// the node's own w_q (1 + P_q(c_0)) as in beta_rel
+template <class L, class C>
+__device__ __forceinline__ void beta_face(int q, const C* cgB, const C* clB, const C* c0g, const C* c0l, C& dbg,
+                                          C& dbl) {
+    constexpr int D = L::D;
+    C dg[D], dl[D], sg[D], sl[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        dg[a] = cgB[a] - c0g[a];
+        dl[a] = clB[a] - c0l[a];
+        sg[a] = cgB[a] + c0g[a];
+        sl[a] = clB[a] + c0l[a];
+    }
+    dbg = p_diff<L>(q, dg, sg);
+    dbl = p_diff<L>(q, dl, sl);
+}
+template <class L, class C>
+__device__ __forceinline__ void beta_wall(int q, const C* c0g, const C* c0l, C& dbg, C& dbl) {
+    C ug2 = C(0), ul2 = C(0);
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) {
+        ug2 += c0g[a] * c0g[a];
+        ul2 += c0l[a] * c0l[a];
+    }
     const C wq = C(L::w[q]);
-    dbg = wq * als * (C(3) * vd + als * even);
-    dbl = wq * as * (-C(3) * vd + as * even);
+    dbg = -wq * poly2(dotc<L>(q, c0g), ug2);
+    dbl = -wq * poly2(dotc<L>(q, c0l), ul2);
+}
+
+// does direction q of a node on the lattice's edge arrive through a wall or
+// through the inlet/outlet plane?  (Reading R15: a wall face wins at corners.)
+template <class L, class WL, class WH>
+__device__ __forceinline__ void bnd_kind(int q, const bool* lo, const bool* hi, int fs, int fa, WL wall_lo,
+                                         WH wall_hi, bool& wall, bool& flow) {
+    wall = false;
+    flow = false;
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) {
+        wall = wall || (lo[a] && L::c[q][a] == 1 && wall_lo(a)) || (hi[a] && L::c[q][a] == -1 && wall_hi(a));
+    }
+    if (!wall && fs >= 0) {
+        const int cfa = fa == 0 ? L::c[q][0] : (fa == 1 ? L::c[q][1] : L::c[q][2]);
+        flow = (fs == 0 && cfa == 1) || (fs == 1 && cfa == -1);
+    }
+}
+
+// record of a node built from the initial fields (stage: alpha_g, u_g,
+// u_l, dp_k as [2 + 2D][n] FP64)
+template <class L, class C>
+__device__ __forceinline__ Rec8<C> stage_rec(const double* stage, long long src, long long n, double a_ref) {
+    constexpr int D = L::D;
+    Rec8<C> r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r.v[k] = C(0);
+    r.v[0] = C(stage[src] - a_ref);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        r.v[1 + a] = C(stage[(1 + a) * n + src]);
+        r.v[1 + D + a] = C(stage[(1 + D + a) * n + src]);
+    }
+    r.v[kDe<D>] = C(3.0 * stage[(1 + 2 * D) * n + src]);
+    return r;
+}
+
+// n_q = f_q - E_q(r0) for a population pulled from a sender with record rs:
+// the stored residual g plus E_q(rs) - E_q(r0), written with the record
+// differences (see Rec8); a0d, a0 = a_r + a0d: gas fraction of r0
+template <class L, class C>
+__device__ __forceinline__ void rebase(int q, const C* g, const Rec8<C>& rs, C a0d, C a0, const C* ug0, const C* ul0,
+                                       C de0, C* n4) {
+    constexpr int D = L::D;
+    const C wq = C(L::w[q]);
+    C dug[D], dul[D], ugs[D], uls[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        ugs[a] = rs.v[1 + a];
+        uls[a] = rs.v[1 + D + a];
+        dug[a] = ugs[a] - ug0[a];
+        dul[a] = uls[a] - ul0[a];
+    }
+    const C cdg = dotc<L>(q, dug), cdl = dotc<L>(q, dul);
+    const C dA = rs.v[0] - a0d;
+    n4[0] = g[0] + wq * ((rs.v[kDe<D>] - de0) + C(3) * cdg);
+    n4[1] = g[1] + wq * (C(3) * cdl);
+    n4[2] = g[2] + wq * (dA + C(3) * (dA * dotc<L>(q, ugs) + a0 * cdg));
+    n4[3] = g[3] + wq * (C(3) * ((C(1) - a0) * cdl - dA * dotc<L>(q, uls)) - dA);
+}
+
+// beta_rel for an upstream node with record rs (the node's own: a0d, a0 =
+// a_r + a0d, al0, u_g0, u_l0); als: alpha_l of the sender, renorm: alpha_l =
+// 1 - alpha_g (then alpha_l,s - alpha_l,0 = -(alpha_g,s - alpha_g,0), exact
+// from the record deviations)
+template <class L, class C>
+__device__ __forceinline__ void beta_from(int q, const Rec8<C>& rs, bool renorm, C ar, C a0d, C a0, C al0, C als,
+                                          const C* ug0, const C* ul0, C& dbg, C& dbl) {
+    constexpr int D = L::D;
+    C dus[D], ddu[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        dus[a] = rs.v[1 + a] - rs.v[1 + D + a];
+        ddu[a] = (rs.v[1 + a] - ug0[a]) - (rs.v[1 + D + a] - ul0[a]);
+    }
+    const C da = rs.v[0] - a0d;
+    beta_rel<L>(q, ar + rs.v[0], als, dus, renorm ? -da : als - al0, da, al0, a0, ddu, dbg, dbl);
 }
 
 // Population layout: each z-plane is a sequence of x-blocks of 64 nodes (rows
@@ -318,7 +563,7 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
     const bool act = x < p.nx && y < p.ny;
     const long long n = p.n;
     const long long node = ((long long)z * p.ny + y) * p.nx + x;
-    const unsigned rb = (unsigned)node * (unsigned)sizeof(Rec4<C>);   // ... in the record array
+    const unsigned rb = (unsigned)node * (unsigned)sizeof(Rec8<C>);   // ... in the record array
     const unsigned cb = (unsigned)node * (unsigned)sizeof(C);         // ... in a scalar array
     const int co[3] = {x, y, z};
     const int nn[3] = {p.nx, p.ny, p.nz};
@@ -333,23 +578,42 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
     // started wave gets its loads in flight ahead of the arithmetic of older
     // waves on the same SIMD (measured: -2 to -3 % on the D2Q9 channel).
     __builtin_amdgcn_s_setprio(3);
+    // The upstream records of the tile (FP32 compute): the tile's nodes and a
+    // one-node halo (the neighbouring planes too in D3Q19) are loaded once
+    // per workgroup into LDS with coalesced loads (periodic axes wrap, other
+    // coordinates clamp: a pull from outside the lattice arrives through a
+    // boundary and its record is not used), so each node's Q - 1 upstream
+    // records come from LDS instead of as many scattered cache loads.
+    constexpr bool kStage = !INIT && sizeof(C) == 4;
+    const int wx = blockDim.x + 2, wy = blockDim.y + 2;
+    if constexpr (kStage) {
+        const int nwin = wx * wy * (D == 3 ? 3 : 1);
+        const int x0 = x - (int)threadIdx.x - 1, y0 = y - (int)threadIdx.y - 1;
+        const int nthr = blockDim.x * blockDim.y;
+        const __amdgpu_buffer_rsrc_t rw = rsrc(b.cf_in);
+        for (int e = threadIdx.y * blockDim.x + threadIdx.x; e < nwin; e += nthr) {
+            const int i = e % wx, jk = e / wx;
+            const int j = jk % wy, k = jk / wy;
+            const int xs = wrap_axis(x0 + i, p.nx, per(0));
+            const int ys = wrap_axis(y0 + j, p.ny, per(1));
+            const int zs = D == 3 ? wrap_axis(z - 1 + k, p.nz, per(2)) : 0;
+            const long long src = ((long long)zs * p.ny + ys) * p.nx + xs;
+            lds_put<D>(lds_win + e, ld_rec_up<D>(rw, (unsigned)src * (unsigned)sizeof(Rec8<float>), 0u, 0.0f));
+        }
+        __syncthreads();
+    }
+    // LDS slot of the upstream node of direction q
+    auto win_at = [&](int q) {
+        return ((int)threadIdx.x + 1 - L::c[q][0]) +
+               wx * (((int)threadIdx.y + 1 - L::c[q][1]) + wy * (D == 3 ? 1 - L::c[q][2] : 0));
+    };
     if (act) {
         const T* pin = static_cast<const T*>(b.pop_in);
-        const Rec4<C>* cfin = static_cast<const Rec4<C>*>(b.cf_in);
+        const Rec8<C>* cfin = static_cast<const Rec8<C>*>(b.cf_in);
         const C* alin = static_cast<const C*>(b.al_in);
         const C* sidein = static_cast<const C*>(b.side_in);
         const C ar = C(p.alpha_ref);
 
-        // a lane whose pulls wrap around a periodic face or cross a boundary
-        bool fix = false;
-#pragma unroll
-        for (int a = 0; a < D; ++a) fix = fix || co[a] == 0 || co[a] == nn[a] - 1;
-        // The interior gather (one block-relative offset per x-shift, shared by
-        // every direction) is kept only where it pays: its registers cost more
-        // waves per SIMD than its addressing saves everywhere except the
-        // periodic D3Q19 step in 16-bit storage (measured).
-        constexpr bool kFastGather = L::D == 3 && BC == kBcPeriodic && sizeof(T) == 2;
-        const bool general = INIT || !kFastGather || __any(fix);
 
         // -------------------------------------------------- boundary layout
         bool lo[3] = {false, false, false}, hi[3] = {false, false, false};
@@ -386,6 +650,10 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
         // step (beta is 1 before streaming, Eqs. (105)-(107)), so its
         // extrapolation is 1 as well
         C cgB[D], clB[D];
+        // (computed where they are used -- before the initial step's gather,
+        // at the edge nodes of a later step after theirs -- so that they hold
+        // no registers through the gather)
+        auto face_values = [&]() {
 #pragma unroll
         for (int a = 0; a < D; ++a) uinG[a] = uinL[a] = ugB[a] = ulB[a] = cgB[a] = clB[a] = C(0);
         if constexpr (CH) {
@@ -437,19 +705,52 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                 }
             }
         }
+        };
+        if constexpr (INIT) face_values();
 
-        // ------------------------------------------------------- gather
-        C f[4][Q];
+        // ---------------------------------- the node's own record at t - 1
+        // The populations are stored relative to the equilibrium part E_q(r)
+        // of their sender's record r (see rec_e): what is reconstructed here
+        // is n_q = f_q - E_q(r0), the pulled population minus the part the
+        // node's own record r0 would give, from the stored residual plus the
+        // differences between the sender's record and r0 -- so the moments
+        // below add small numbers to r0's values instead of summing large
+        // ones.  The initial step takes r0 from the initial fields.
+        Rec8<C> r0;
         if constexpr (INIT) {
-            // local equilibria of the initial fields (deviation form)
-            const C a0 = C(b.stage[node]);
-            C ug0[D], ul0[D];
+            r0 = stage_rec<L, C>(b.stage, node, n, p.alpha_ref);
+        } else {
+            r0 = ld_rec8(rsrc(cfin), rb, 0u, C(0));
+        }
+        const C a0d = r0.v[0], a0 = ar + a0d, de0 = r0.v[kDe<D>];
+        C ug0[D], ul0[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            ug0[a] = r0.v[1 + a];
+            ul0[a] = r0.v[1 + D + a];
+        }
+        const C lam_prev = D == 2 ? r0.v[kLam] : C(0);  // lagged Lambda' of the last refresh (D2Q9)
+        // the node's own imposed velocities of the source schemes (Eq. (97))
+        C al0 = C(1) - a0;
+        if constexpr (!INIT) {
+            if (!p.renorm) al0 = *at(alin, cb);
+        }
+        C c0g[D], c0l[D];
+        auto own_c = [&]() {
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                ug0[a] = C(b.stage[(1 + a) * n + node]);
-                ul0[a] = C(b.stage[(1 + D + a) * n + node]);
+                const C du0 = ug0[a] - ul0[a];
+                c0g[a] = al0 * du0;
+                c0l[a] = -a0 * du0;
             }
-            const C de0 = C(3.0 * b.stage[(1 + 2 * D) * n + node]);
+        };
+        if constexpr (INIT) own_c();
+
+        // ------------------------------------------------------- gather
+        C f[4][Q];              // n_q of f_g, f_l, f_ag, f_al
+        C Sg = C(0), Sl = C(0);  // continuity sources from f_b (Eq. (107))
+        if constexpr (INIT) {
+            // local equilibria of the initial fields: n_q = f^eq_q - E_q(r0)
             C us0g = C(0), us0l = C(0);
 #pragma unroll
             for (int a = 0; a < D; ++a) {
@@ -462,40 +763,35 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
             for (int q = 0; q < Q; ++q) {
                 const C wq = C(L::w[q]);
                 const C cug = dotc<L>(q, ug0), cul = dotc<L>(q, ul0);
+                const C qg = C(4.5) * cug * cug - C(1.5) * us0g, ql = C(4.5) * cul * cul - C(1.5) * us0l;
                 const C el = q == 0 ? -k0 * de0 * C(p.invR) : de0 * C(p.invR);
-                f[0][q] = wq * (de0 + poly2(cug, us0g));
-                f[1][q] = wq * (el + poly2(cul, us0l));
-                f[2][q] = wq * ((a0 - ar) + a0 * poly2(cug, us0g));
-                f[3][q] = wq * ((ar - a0) + (C(1) - a0) * poly2(cul, us0l));
+                f[0][q] = wq * qg;
+                f[1][q] = wq * (el + ql);
+                f[2][q] = wq * a0 * qg;
+                f[3][q] = wq * (C(1) - a0) * ql;
             }
-        } else if (!general) {
-            // Interior wavefront (64 lanes = one x-block, see pop_in_plane): the
-            // source of direction q lies in x-block xb of row y - c_y (plane
-            // z - c_z), or in its neighbour block for the lane at the block
-            // edge.  The block part, taken from block xb - 1, is uniform
-            // across the wave, but it derives from the thread index, so the
-            // compiler cannot prove it: as an SGPR offset it would wrap each
-            // access in a loop over lane values.  It is added to one of the
-            // three per-lane parts (one per c_x, computed once) instead.
-            const int xb = x >> 6, xl = x & 63;
-            unsigned vo[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int src = xl - (k - 1);
-                vo[k] = (unsigned)((src < 0 ? 63 * 4 : (src > 63 ? 2 * kBlk : kBlk + src * 4)) * (int)sizeof(T));
-            }
-            __amdgpu_buffer_rsrc_t rp[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                if (D == 3 || k == 1) rp[k] = rsrc(pin + (long long)(z - (k - 1)) * p.plane);
+            // f_b "as streamed" from the initial imposed velocities
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                const long long blk = (long long)(y - L::c[q][1]) * p.nxb + (xb - 1);
-                const unsigned so = (unsigned)((blk * kBlk + q * 256) * (long long)sizeof(T));
-                C g4[4];
-                Pop4<T>::ld(rp[L::c[q][2] + 1], vo[L::c[q][0] + 1] + so, 0u, g4);
-#pragma unroll
-                for (int s = 0; s < 4; ++s) f[s][q] = g4[s];
+                bool wall = false, flow = false;
+                if constexpr (CH) {
+                    if (edge) bnd_kind<L>(q, lo, hi, fs, fa, wall_lo, wall_hi, wall, flow);
+                }
+                C dbg, dbl;
+                if (wall) {
+                    beta_wall<L>(q, c0g, c0l, dbg, dbl);
+                } else if (flow) {
+                    beta_face<L>(q, cgB, clB, c0g, c0l, dbg, dbl);
+                } else {
+                    const int xs = wrap_axis(x - L::c[q][0], p.nx, per(0));
+                    const int ys = wrap_axis(y - L::c[q][1], p.ny, per(1));
+                    const int zs = wrap_axis(z - L::c[q][2], p.nz, per(2));
+                    const Rec8<C> rs =
+                        stage_rec<L, C>(b.stage, ((long long)zs * p.ny + ys) * p.nx + xs, n, p.alpha_ref);
+                    beta_from<L>(q, rs, true, ar, a0d, a0, al0, C(1) - (ar + rs.v[0]), ug0, ul0, dbg, dbl);
+                }
+                Sg -= dbg;
+                Sl -= dbl;
             }
         } else {
             // direction q of this lane arrives through a wall or the
@@ -503,22 +799,15 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
             // start from the node's own post-collision population of the
             // opposite direction, so the gather loads that one in place of
             // the pull (one batch of Q loads, no second, dependent load)
-            unsigned bmask = 0u;
+            unsigned bmask = 0u, wmask = 0u;
             if constexpr (CH) {
                 if (edge) {
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
                         bool wall = false, flow = false;
-#pragma unroll
-                        for (int a = 0; a < D; ++a) {
-                            wall = wall || (lo[a] && L::c[q][a] == 1 && wall_lo(a)) ||
-                                   (hi[a] && L::c[q][a] == -1 && wall_hi(a));
-                        }
-                        if (!wall && fs >= 0) {
-                            const int cfa = fa == 0 ? L::c[q][0] : (fa == 1 ? L::c[q][1] : L::c[q][2]);
-                            flow = (fs == 0 && cfa == 1) || (fs == 1 && cfa == -1);
-                        }
+                        bnd_kind<L>(q, lo, hi, fs, fa, wall_lo, wall_hi, wall, flow);
                         if (wall || flow) bmask |= 1u << q;
+                        if (wall) wmask |= 1u << q;
                     }
                 }
             }
@@ -532,138 +821,113 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                 const int zs = L::c[q][2] == 0 ? z : (bnd ? z : wrap_axis(z - L::c[q][2], p.nz, per(2)));
                 C g4[4];
                 Pop4<T>::ld(rsrc(pin + (long long)zs * p.plane),
-                            pop_in_plane<L>(p, xs, ys, bnd ? L::opp[q] : q) * (unsigned)sizeof(T), 0, g4);
+                            pop_in_plane<L>(p, xs, ys, bnd ? L::opp[q] : q) * (unsigned)sizeof(T), 0, g4, p, q == 0);
 #pragma unroll
                 for (int s = 0; s < 4; ++s) f[s][q] = g4[s];
             }
+            // The upstream records and the rebase onto the node's own
+            // record, one direction at a time (staged: short LDS reads; else
+            // one batch of loads); a direction that arrives through a
+            // boundary keeps the loaded residual of its opposite direction.
+            auto pass = [&](auto rn) {
+                constexpr bool renorm = decltype(rn)::value;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const bool bnd = (bmask >> q) & 1u;
+                if (kStage && bnd) continue;
+                const int xs = bnd ? x : wrap_axis(x - L::c[q][0], p.nx, per(0));
+                const int ys = bnd ? y : wrap_axis(y - L::c[q][1], p.ny, per(1));
+                const int zs = bnd ? z : wrap_axis(z - L::c[q][2], p.nz, per(2));
+                const long long src = ((long long)zs * p.ny + ys) * p.nx + xs;
+                Rec8<C> rs = r0;
+                if (q != 0) {
+                    if constexpr (kStage)
+                        rs = lds_get<D>(lds_win + win_at(q));
+                    else
+                        rs = ld_rec_up<D>(rsrc(cfin), (unsigned)src * (unsigned)sizeof(Rec8<C>), 0u, C(0));
+                }
+                const C g4[4] = {f[0][q], f[1][q], f[2][q], f[3][q]};
+                C n4[4];
+                rebase<L>(q, g4, rs, a0d, a0, ug0, ul0, de0, n4);
+                C als;
+                if constexpr (renorm)
+                    als = C(1) - (ar + rs.v[0]);
+                else
+                    als = *at(alin, (unsigned)src * (unsigned)sizeof(C));
+                C dbg, dbl;
+                beta_from<L>(q, rs, renorm, ar, a0d, a0, al0, als, ug0, ul0, dbg, dbl);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) f[s][q] = bnd ? g4[s] : n4[s];  // bnd: residual of the opposite direction
+                Sg -= bnd ? C(0) : dbg;
+                Sl -= bnd ? C(0) : dbl;
+            }
+            };
+            if (p.renorm)
+                pass(std::true_type{});
+            else
+                pass(std::false_type{});
             if constexpr (CH) {
                 if (edge) {
+                    face_values();
+                    own_c();
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
                         if (!((bmask >> q) & 1u)) continue;
-                        bool wall = false;
-#pragma unroll
-                        for (int a = 0; a < D; ++a) {
-                            wall = wall || (lo[a] && L::c[q][a] == 1 && wall_lo(a)) ||
-                                   (hi[a] && L::c[q][a] == -1 && wall_hi(a));
-                        }
-                        C fo[4];  // the node's own population of the opposite direction
+                        const bool wall = (wmask >> q) & 1u;
+                        C fo[4];  // residual of the node's own post-collision population of the opposite direction
 #pragma unroll
                         for (int s = 0; s < 4; ++s) fo[s] = f[s][q];
                         const C wq = C(L::w[q]);
+                        const C cg0 = dotc<L>(q, ug0), cl0 = dotc<L>(q, ul0);
                         if (wall) {
                             // half-way bounce-back, zero wall velocity
-#pragma unroll
-                            for (int s = 0; s < 4; ++s) f[s][q] = fo[s];
-                        } else if (ftype == EELBM_BC_INLET) {
-                            C usg = C(0), usl = C(0);
-#pragma unroll
-                            for (int a = 0; a < D; ++a) {
-                                usg += uinG[a] * uinG[a];
-                                usl += uinL[a] * uinL[a];
-                            }
-                            const C cug = dotc<L>(q, uinG), cul = dotc<L>(q, uinL);
-                            // BB(I), Eq. (163): + f_I(-u) - f_I(u) at q* = 6 w v_q.u
-                            f[0][q] = fo[0] + C(6) * wq * cug;
-                            f[1][q] = fo[1] + C(6) * wq * cul;
-                            // EQ(S) with the imposed alpha and velocity
-                            f[2][q] = wq * ((ain - ar) + ain * poly2(cug, usg));
-                            f[3][q] = wq * ((ar - ain) + (C(1) - ain) * poly2(cul, usl));
+                            f[0][q] = fo[0] - C(6) * wq * cg0;
+                            f[1][q] = fo[1] - C(6) * wq * cl0;
+                            f[2][q] = fo[2] - C(6) * wq * a0 * cg0;
+                            f[3][q] = fo[3] - C(6) * wq * (C(1) - a0) * cl0;
+                            C dbg, dbl;
+                            beta_wall<L>(q, c0g, c0l, dbg, dbl);
+                            Sg -= dbg;
+                            Sl -= dbl;
                         } else {
-                            C usg = C(0), usl = C(0);
+                            if (ftype == EELBM_BC_INLET) {
+                                C usg = C(0), usl = C(0);
 #pragma unroll
-                            for (int a = 0; a < D; ++a) {
-                                usg += ugB[a] * ugB[a];
-                                usl += ulB[a] * ulB[a];
+                                for (int a = 0; a < D; ++a) {
+                                    usg += uinG[a] * uinG[a];
+                                    usl += uinL[a] * uinL[a];
+                                }
+                                const C cug = dotc<L>(q, uinG), cul = dotc<L>(q, uinL);
+                                // BB(I), Eq. (163): + f_I(-u) - f_I(u) at q* = 6 w v_q.u
+                                f[0][q] = fo[0] + C(6) * wq * (cug - cg0);
+                                f[1][q] = fo[1] + C(6) * wq * (cul - cl0);
+                                // EQ(S) with the imposed alpha and velocity
+                                f[2][q] = wq * (((ain - ar) - a0d) + ain * poly2(cug, usg) - C(3) * a0 * cg0);
+                                f[3][q] = wq * (((ar - ain) + a0d) + (C(1) - ain) * poly2(cul, usl) -
+                                                C(3) * (C(1) - a0) * cl0);
+                            } else {
+                                C usg = C(0), usl = C(0);
+#pragma unroll
+                                for (int a = 0; a < D; ++a) {
+                                    usg += ugB[a] * ugB[a];
+                                    usl += ulB[a] * ulB[a];
+                                }
+                                const C cug = dotc<L>(q, ugB), cul = dotc<L>(q, ulB);
+                                const C eg = C(4.5) * cug * cug - C(1.5) * usg, el = C(4.5) * cul * cul - C(1.5) * usl;
+                                // ABB(I), Eq. (164), eps = phi = 1
+                                f[0][q] = -fo[0] + C(2) * wq * (eg - de0);
+                                f[1][q] = -fo[1] + C(2) * wq * el;
+                                // ABB(S)
+                                f[2][q] = -fo[2] + C(2) * wq * (((agB - ar) - a0d) + agB * eg);
+                                f[3][q] = -fo[3] + C(2) * wq * (((alB - (C(1) - ar)) + a0d) + alB * el);
                             }
-                            const C cug = dotc<L>(q, ugB), cul = dotc<L>(q, ulB);
-                            const C eg = C(4.5) * cug * cug - C(1.5) * usg, el = C(4.5) * cul * cul - C(1.5) * usl;
-                            // ABB(I), Eq. (164), eps = phi = 1
-                            f[0][q] = -fo[0] + C(2) * wq * eg;
-                            f[1][q] = -fo[1] + C(2) * wq * el;
-                            // ABB(S)
-                            f[2][q] = -fo[2] + C(2) * wq * ((agB - ar) + agB * eg);
-                            f[3][q] = -fo[3] + C(2) * wq * ((alB - (C(1) - ar)) + alB * el);
+                            C dbg, dbl;
+                            beta_face<L>(q, cgB, clB, c0g, c0l, dbg, dbl);
+                            Sg -= dbg;
+                            Sl -= dbl;
                         }
                     }
                 }
-            }
-        }
-
-        // ---------- continuity sources from f_b (Eq. (107)) and own record
-        C Sg = C(0), Sl = C(0), lam_prev = C(0);
-        if (!general) {
-            // descriptor base moved back by the largest pull shift so that
-            // every per-direction SGPR offset is non-negative
-            const long long ms = (long long)p.nx + 1 + (D == 3 ? nxy : 0);
-            const __amdgpu_buffer_rsrc_t rc = rsrc(cfin - ms);
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const long long dq = -((long long)L::c[q][0] + (long long)L::c[q][1] * p.nx + L::c[q][2] * nxy);
-                const Rec4<C> r = ld_rec(rc, rb, (unsigned)((dq + ms) * (long long)sizeof(Rec4<C>)), C(0));
-                C du[D];
-#pragma unroll
-                for (int a = 0; a < D; ++a) du[a] = r.v[1 + a];
-                if (q == 0 && D == 2) lam_prev = r.v[3];
-                const C als = p.renorm ? C(1) - r.v[0] : *at(alin + dq, cb);
-                C dbg, dbl;
-                beta_dev<L>(q, r.v[0], als, du, dbg, dbl);
-                Sg -= dbg;
-                Sl -= dbl;
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const C wq = C(L::w[q]);
-                bool wall = false, flow = false;
-                if constexpr (CH) {
-                    if (edge) {
-#pragma unroll
-                        for (int a = 0; a < D; ++a) {
-                            wall = wall || (lo[a] && L::c[q][a] == 1 && wall_lo(a)) ||
-                                   (hi[a] && L::c[q][a] == -1 && wall_hi(a));
-                        }
-                        if (!wall && fs >= 0) {
-                            const int cfa = fa == 0 ? L::c[q][0] : (fa == 1 ? L::c[q][1] : L::c[q][2]);
-                            flow = (fs == 0 && cfa == 1) || (fs == 1 && cfa == -1);
-                        }
-                    }
-                }
-                if (wall) continue;  // EQ(S)(1, 0) = w_q: zero deviation
-                C dbg, dbl;
-                if (flow) {
-                    C usg = C(0), usl = C(0);
-#pragma unroll
-                    for (int a = 0; a < D; ++a) {
-                        usg += cgB[a] * cgB[a];
-                        usl += clB[a] * clB[a];
-                    }
-                    dbg = wq * poly2(dotc<L>(q, cgB), usg);
-                    dbl = wq * poly2(dotc<L>(q, clB), usl);
-                } else {
-                    const int xs = wrap_axis(x - L::c[q][0], p.nx, per(0));
-                    const int ys = wrap_axis(y - L::c[q][1], p.ny, per(1));
-                    const int zs = wrap_axis(z - L::c[q][2], p.nz, per(2));
-                    const long long src = ((long long)zs * p.ny + ys) * p.nx + xs;
-                    C as, als, du[D];
-                    if constexpr (INIT) {
-                        as = C(b.stage[src]);
-                        als = C(1) - as;
-#pragma unroll
-                        for (int a = 0; a < D; ++a)
-                            du[a] = C(b.stage[(1 + a) * n + src] - b.stage[(1 + D + a) * n + src]);
-                    } else {
-                        const Rec4<C> r = *at(cfin, (unsigned)src * (unsigned)sizeof(Rec4<C>));
-                        as = r.v[0];
-#pragma unroll
-                        for (int a = 0; a < D; ++a) du[a] = r.v[1 + a];
-                        if (q == 0 && D == 2) lam_prev = r.v[3];
-                        als = p.renorm ? C(1) - as : *at(alin, (unsigned)src * (unsigned)sizeof(C));
-                    }
-                    beta_dev<L>(q, as, als, du, dbg, dbl);
-                }
-                Sg -= dbg;
-                Sl -= dbl;
             }
         }
 
@@ -679,15 +943,28 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
 
         __builtin_amdgcn_s_setprio(0);
         // ------------------------------------------------------- moments
-        C deg = C(0), del = C(0), sag = C(0), sal = C(0);
-        C ug[D], ul[D], Jg[D], Jl[D], Pg[NPI], Pl[NPI];
+        // the moments of E(r0) (Eqs. (40)-(41), (73)-(74)) plus those of the
+        // residuals: sum_q w_q v_q = 0, sum_q w_q v_q v_q = c_s^2 I and the
+        // third moment of the weights vanishes
+        C sdeg = C(0), del = C(0), sag = a0d, sal = -a0d;
+        C sug[D], sul[D], Jg[D], Jl[D], Pg[NPI], Pl[NPI];
 #pragma unroll
-        for (int a = 0; a < D; ++a) ug[a] = ul[a] = Jg[a] = Jl[a] = C(0);
+        for (int a = 0; a < D; ++a) {
+            sug[a] = C(0);
+            sul[a] = C(0);
+            Jg[a] = a0 * ug0[a];
+            Jl[a] = (C(1) - a0) * ul0[a];
+        }
 #pragma unroll
-        for (int k = 0; k < NPI; ++k) Pg[k] = Pl[k] = C(0);
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int bb = a; bb < D; ++bb) {
+                Pg[sym<D>(a, bb)] = a == bb ? third * de0 : C(0);
+                Pl[sym<D>(a, bb)] = C(0);
+            }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            deg += f[0][q];  // Eq. (40), deviation from 1
+            sdeg += f[0][q];  // Eq. (40), deviation from 1
             del += f[1][q];
             sag += f[2][q];  // Eq. (73), deviation from alpha_r
             sal += f[3][q];  // deviation from 1 - alpha_r
@@ -695,8 +972,8 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
             for (int a = 0; a < D; ++a) {
                 const int ca = L::c[q][a];
                 if (ca != 0) {  // Eqs. (41), (74)
-                    ug[a] += ca * f[0][q];
-                    ul[a] += ca * f[1][q];
+                    sug[a] += ca * f[0][q];
+                    sul[a] += ca * f[1][q];
                     Jg[a] += ca * f[2][q];
                     Jl[a] += ca * f[3][q];
                 }
@@ -710,6 +987,27 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                 }
             }
         }
+        // The phase velocities and the gas density deviation are the
+        // record's values plus the residual moments.  The sum is taken in
+        // FP64 (exact for two FP32 terms); the step continues with its FP32
+        // value, and the rounding remainder (eug, eul, ede) is kept in the
+        // stored residuals (see the collisions), so that carrying u and
+        // eps_g - 1 in the FP32 record loses nothing from step to step.
+        using A = double;
+        A ugA[D], ulA[D];
+        C ug[D], ul[D], eug[D], eul[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            ugA[a] = A(ug0[a]) + A(sug[a]);
+            ulA[a] = A(ul0[a]) + A(sul[a]);
+            ug[a] = C(ugA[a]);
+            ul[a] = C(ulA[a]);
+            eug[a] = C(ugA[a] - A(ug[a]));
+            eul[a] = C(ulA[a] - A(ul[a]));
+        }
+        const A degA = A(de0) + A(sdeg);
+        const C deg = C(degA);
+        const C ede = C(degA - A(deg));
         const C ag = ar + sag;               // raw zeroth moments
         const C al_raw = (C(1) - ar) + sal;
 
@@ -721,14 +1019,15 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                 // a_g + a_l = 1 so that FP32 keeps the small correction exactly
                 const C e = sag + sal;  // a_g + a_l - 1
                 const C corr = ag * e * rcp(C(1) + e);
-                alg = ag - corr;
                 dag = sag - corr;
             } else {
                 const C Bg = clamp01(ag), Bl = clamp01(al_raw);
                 const C den = Bg + Bl;
-                alg = den > C(0) ? Bg * rcp(den) : C(0);
-                dag = alg - ar;
+                dag = (den > C(0) ? Bg * rcp(den) : C(0)) - ar;
             }
+            // alpha_g from its deviation, the value the record carries (the
+            // stored populations are relative to it)
+            alg = ar + dag;
             all = C(1) - alg;
         } else {
             alg = ag;
@@ -852,10 +1151,16 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
         const long long oblk = ((long long)y * p.nxb + (x >> 6)) * kBlk;
         const unsigned vl = (unsigned)((x & 63) * 4 * (int)sizeof(T));
         {
-            // BGK relaxation plus forcing, f + omega (f^eq - f) + f^L, regrouped
-            // as (1 - omega) f + w_q [A + omega s(c.u) + 3 c.G] with the
-            // node constants A hoisted out of the direction loop and
-            // s(x) = 3 x + 9/2 x^2 shared by the two sets of a phase
+            // BGK relaxation plus forcing, f* = f + omega (f^eq - f) + f^L,
+            // stored as the residual f* - E_q(r) against this node's new
+            // record r: with f = E_q(r0) + n_q,
+            //   f* - E_q(r) = (1 - omega) [n_q + E_q(r0) - E_q(r)]
+            //               + omega [f^eq_q - E_q(r)] + f^L_q,
+            // where E_q(r0) - E_q(r) depends only on the differences between
+            // the old and new record and f^eq - E(r) holds only the
+            // second-order and rest-population parts plus the FP32 rounding
+            // remainders of r -- every term is small, so neither the
+            // arithmetic nor the storage rounds a large value.
             const C w0 = C(L::w[0]);
             const C k0 = (C(1) - w0) / w0;
             const C el0 = del + k0 * (del - dphiel);  // eps_l eta_0(phi) - 1, Eq. (38)
@@ -863,42 +1168,59 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
             const C el0p = C(1) + k0 * (C(1) - C(p.psi_l));
             const C og = C(p.omega_g), ol = C(p.omega_l), oag = C(p.omega_ag), oal = C(p.omega_al);
             const C kog = C(1) - og, kol = C(1) - ol, koa = C(1) - oag, kob = C(1) - oal;
-            // Eq. (37) with phi = 1 (gas) and phi of Eq. (32) (liquid), Eq. (42)
-            const C bg = og * (deg - C(1.5) * usg), bl = ol * (dphiel - C(1.5) * usl);
-            const C Ag = bg + S2g * C(p.psi_g), Ag0 = bg + S2g * eg0;
-            const C Al = bl + S2l * C(p.psi_l), Al0 = ol * (el0 - C(1.5) * usl) + S2l * el0p;
-            // Eq. (72) for the two volume-fraction schemes
-            const C Aa = oag * (dag - C(1.5) * alg * usg), Ba = oag * alg;
-            const C Ab = oal * (dal - C(1.5) * all * usl), Bb = oal * all;
-            C G3g[D], G3l[D];
+            // rest and non-rest parts of f^eq - E(r) and f^L, Eqs. (37), (42)
+            const C Bg = S2g * C(p.psi_g), Bg0 = S2g * eg0;
+            const C Bl = ol * dphiel + S2l * C(p.psi_l), Bl0 = ol * el0 + S2l * el0p;
+            // old minus new record values
+            const C dA = a0d - dag;
+            const C alE = C(1) - alg;  // f_al reference of the new record
+            const C xl = all - alE;    // 0 with the renormalisation
+            // every direction-dependent term is linear in v_q apart from the
+            // second-order equilibria: the per-set vectors V collect them
+            // (the record differences, the rounding remainders and 3 F),
+            // A the direction-independent parts
+            const C Ag = kog * (de0 - deg) + og * ede, A2 = koa * dA, A3 = oal * xl - kob * dA;
+            C Vg[D], Vl[D], V2[D], V3[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                G3g[a] = C(3) * Gg[a];
-                G3l[a] = C(3) * Gl[a];
+                const C dug = ug0[a] - ug[a], dul = ul0[a] - ul[a];
+                Vg[a] = C(3) * (kog * dug + og * eug[a] + Gg[a]);
+                Vl[a] = C(3) * (kol * dul + ol * eul[a] + Gl[a]);
+                V2[a] = C(3) * koa * (dA * ug0[a] + alg * dug);
+                V3[a] = C(3) * (kob * (alE * dul - dA * ul0[a]) + oal * xl * ul[a]);
             }
+            const C ogA = oag * alg, olA = oal * all;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const C wq = C(L::w[q]);
                 const C cug = dotc<L>(q, ug), cul = dotc<L>(q, ul);
-                const C sg2 = cug * (C(3) + C(4.5) * cug), sl2 = cul * (C(3) + C(4.5) * cul);
-                const C o0 = kog * f[0][q] + wq * ((q == 0 ? Ag0 : Ag) + og * sg2 + dotc<L>(q, G3g));
-                const C o1 = kol * f[1][q] + wq * ((q == 0 ? Al0 : Al) + ol * sl2 + dotc<L>(q, G3l));
-                const C o2 = koa * f[2][q] + wq * (Aa + Ba * sg2);
-                const C o3 = kob * f[3][q] + wq * (Ab + Bb * sl2);
+                const C qg = C(4.5) * cug * cug - C(1.5) * usg, ql = C(4.5) * cul * cul - C(1.5) * usl;
+                const C o0 = kog * f[0][q] + wq * ((Ag + (q == 0 ? Bg0 : Bg)) + dotc<L>(q, Vg) + og * qg);
+                const C o1 = kol * f[1][q] + wq * ((q == 0 ? Bl0 : Bl) + dotc<L>(q, Vl) + ol * ql);
+                const C o2 = koa * f[2][q] + wq * (A2 + dotc<L>(q, V2) + ogA * qg);
+                const C o3 = kob * f[3][q] + wq * (A3 + dotc<L>(q, V3) + olA * ql);
                 const C o4[4] = {o0, o1, o2, o3};
                 const unsigned vq = vl + (unsigned)((oblk + q * 256) * (long long)sizeof(T));
-                Pop4<T>::template st<NTS ? kNT : 0>(ro, vq, 0u, o4);
+                Pop4<T>::template st<NTS ? kNT : 0>(ro, vq, 0u, o4, p, q == 0);
             }
         }
 
         // ------------ imposed-velocity record of the source schemes (Eq. (97))
+        // and reference of the stored populations (rec_e)
         {
-            Rec4<C> r;
-            r.v[0] = alg;
+            Rec8<C> r;
+            r.v[0] = dag;
 #pragma unroll
-            for (int a = 0; a < D; ++a) r.v[1 + a] = ug[a] - ul[a];
-            if (D == 2) r.v[3] = Laml;  // carried forward for the lagged drag
-            st_rec(rsrc(b.cf_out), rb, r);
+            for (int a = 0; a < D; ++a) {
+                r.v[1 + a] = ug[a];
+                r.v[1 + D + a] = ul[a];
+            }
+            if (D == 2) {
+                r.v[kLam] = Laml;  // carried forward for the lagged drag
+                r.v[7] = C(0);
+            }
+            r.v[kDe<D>] = deg;
+            st_rec8(rsrc(b.cf_out), rb, r);
             if (!p.renorm) *at(static_cast<C*>(b.al_out), cb) = all;
         }
 
@@ -942,23 +1264,23 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
             m[n + node] = double(all);
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                m[(2 + a) * n + node] = double(ug[a]);
-                m[(2 + D + a) * n + node] = double(ul[a]);
+                m[(2 + a) * n + node] = double(ugA[a]);
+                m[(2 + D + a) * n + node] = double(ulA[a]);
             }
-            m[(2 + 2 * D) * n + node] = double(deg) / 3.0;
+            m[(2 + 2 * D) * n + node] = double(degA) / 3.0;
         }
         if (OUT && ctl.write_diag) {
             dsum[0] = double(ar) + double(sag);
             dsum[1] = (1.0 - double(ar)) + double(sal);
             dsum[2] = double(alg);
             dsum[3] = double(all);
-            dsum[4] = double(deg);
+            dsum[4] = double(degA);
             dsum[5] = double(del);
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                dsum[6 + a] = double(ug[a]);
-                dsum[9 + a] = double(ul[a]);
-                dsum[12 + a] = p.rho_g * double(alg) * double(ug[a]) + p.rho_l * double(all) * double(ul[a]);
+                dsum[6 + a] = double(ugA[a]);
+                dsum[9 + a] = double(ulA[a]);
+                dsum[12 + a] = p.rho_g * double(alg) * double(ugA[a]) + p.rho_l * double(all) * double(ulA[a]);
             }
             dsum[15] = double(dag) - double(sag);
         }
@@ -996,6 +1318,7 @@ __device__ __forceinline__ long long xcd_tile(long long id, long long nb, int re
     const long long per = nb >> 3;
     return id < per * 8 ? (id & 7) * per + (id >> 3) : id;
 }
+
 
 template <class L, class T, int BC, bool INIT, bool OUT, bool NTS>
 __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b, const KCtl ctl) {
@@ -1108,9 +1431,18 @@ __global__ void __launch_bounds__(256) k_convert(const double* src, void* dst, i
 }
 
 // ------------------------------------------------------------ launchers
+// LDS bytes of the staged record window of a tile (0: records read from
+// memory -- the initial step and FP64 compute)
+template <class L, class T, bool INIT>
+static unsigned window_bytes(dim3 bl) {
+    if (INIT || sizeof(typename Compute<T>::C) != 4) return 0u;
+    return (bl.x + 2) * (bl.y + 2) * (L::D == 3 ? 3u : 1u) * (unsigned)sizeof(Rec8<float>);
+}
+
 template <class L, class T, int BC, bool INIT, bool OUT, bool NTS = false>
 static hipError_t go(const KParams& p, const KBuffers& b, const KCtl& c, dim3 g, dim3 bl, hipStream_t s) {
-    hipLaunchKernelGGL((k_step<L, T, BC, INIT, OUT, NTS>), g, bl, 0, s, p, b, c);
+    const unsigned lds = window_bytes<L, T, INIT>(bl);
+    hipLaunchKernelGGL((k_step<L, T, BC, INIT, OUT, NTS>), g, bl, lds, s, p, b, c);
     return hipGetLastError();
 }
 
@@ -1164,15 +1496,16 @@ template <class L, class T, bool OUT, bool NTS>
 static hipError_t gob_out(int bc, const BatchLattice* lat, const uint2* work, long long nwork,
                           const long long* clock, int k, int write_last, dim3 block, hipStream_t s) {
     const dim3 g((unsigned)nwork);
+    const unsigned lds = window_bytes<L, T, false>(block);
     switch (bc) {
         case kBcPeriodic:
-            hipLaunchKernelGGL((k_step_batch<L, T, kBcPeriodic, OUT, NTS>), g, block, 0, s, lat, work, clock, k, write_last);
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcPeriodic, OUT, NTS>), g, block, lds, s, lat, work, clock, k, write_last);
             break;
         case kBcGeneric:
-            hipLaunchKernelGGL((k_step_batch<L, T, kBcGeneric, OUT, NTS>), g, block, 0, s, lat, work, clock, k, write_last);
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcGeneric, OUT, NTS>), g, block, lds, s, lat, work, clock, k, write_last);
             break;
         case kBcColumn:
-            hipLaunchKernelGGL((k_step_batch<L, T, kBcColumn, OUT, NTS>), g, block, 0, s, lat, work, clock, k, write_last);
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcColumn, OUT, NTS>), g, block, lds, s, lat, work, clock, k, write_last);
             break;
         default: return hipErrorInvalidValue;
     }

@@ -11,18 +11,16 @@ pytestmark = pytest.mark.gpu
 
 FP64_TOL = None  # rel-L2 1e-10 or RMS 1e-13, see parity.check
 FP32_TOL = 1e-5
-# The C1 box in FP32 storage: delta p_k there is ~1e-3 of the velocity part
-# of the stored deviations (|u| ~ 6e-4, |delta p_k| ~ 6e-7), so rounding the
-# stored deviations to FP32 alone -- the oracle's own FP64 step with its
-# populations rounded each step -- already gives rel-L2 1.7e-5 on delta p_k
-# after 1000 steps (test_oracle_scheme.test_fp32_storage_floor_on_box); the
-# FP32 arithmetic of the step adds a factor ~3.  Bound: 10x that floor.
-BOX_FP32_TOL = {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5, "dp_k": 1.7e-4}
-# The D3Q19 periodic boxes below are the same situation after 60 steps:
-# rounding the stored deviations to FP32 alone gives rel-L2 3.1e-6 (12 x 14 x
-# 13) and 4.8e-6 (192 x 6 x 8) on delta p_k
-# (test_oracle_scheme.test_fp32_storage_floor_d3q19_periodic); bound 10x.
-D3_BOX_FP32_TOL = {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5, "dp_k": 5e-5}
+# The C1 box in FP32 storage, delta p_k only: there delta p_k (~6e-7) is
+# ~1e-3 of |u| (~6e-4).  Storing the residuals in FP32 alone (the FP64 oracle
+# with its populations rounded to the stored format every step) costs 4e-8
+# on delta p_k after 1000 steps, and the same FP32 storage under FP64
+# arithmetic measures 3.9e-8 (MI355X); the FP32 arithmetic of the step
+# rounds the momentum update at ~2.5e-8 of |u| and the acoustic response
+# carries that into delta p_k at 1.1e-5 (measured 1.08e-5).  Bound: 2e-5.
+BOX_FP32_TOL = {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5, "dp_k": 2e-5}
+# the D3Q19 periodic boxes meet the common bound (delta p_k 2.3e-6 / 3.5e-6)
+D3_BOX_FP32_TOL = FP32_TOL
 
 
 @pytest.fixture(scope="module")
@@ -230,6 +228,44 @@ def test_launch_shape_does_not_change_results():
         g.set_launch(32, 8)
 
 
+def d3q19_channel(nx=70, ny=9, nz=12):
+    cfg = workloads._base("D3Q19", nx=nx, ny=ny, nz=nz, rho_l=100.0, drag="cgw", kappa_I=1e-3,
+                          g_hat=1e-6 / 99.0, up_axis=2, gamma=1.0, n_gamma=4,
+                          bc={"x-": "wall", "x+": "wall", "y-": "wall", "y+": "wall", "z-": "inlet", "z+": "outlet"},
+                          alpha_in_max=0.1, alpha_in_min=0.01, ug_in_max=3e-3, ug_in_min=3e-4,
+                          ul_in_max=5e-4, ul_in_min=0.0, n_ramp=20.0)
+    rng = np.random.default_rng(7)
+    f = {k: _resize3(v, (nz, ny, nx))
+         for k, v in workloads.smooth_random_3d(8, seed=6, alpha0=0.05, amp_a=0.02).items()}
+    f["inlet_noise"] = 1.0 + 0.1 * rng.uniform(-1, 1, (ny, nx))
+    return cfg, f
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_launch_shape_does_not_change_results_d3q19(storage):
+    """D3Q19 with staged record windows (three planes of a tile and its halo
+    in LDS): every allowed tile shape gives bit-identical fields, on a
+    channel (walls, inlet, outlet) whose sizes are not multiples of the
+    tiles; a tile whose window exceeds the workgroup's LDS is refused
+    (FP64 reads its records from memory and takes any tile)."""
+    from paper_2409_10399_amd import EelbmError
+    cfg, f = d3q19_channel()
+    ref = None
+    for shape in [(64, 4, 1), (128, 2, 0), (64, 1, 1), (64, 2, 0)]:
+        g = run_gpu(cfg, f, 0, storage)
+        g.set_launch(*shape)
+        g.advance(12)
+        out = {k: g.read(k) for k in FIELDS}
+        if ref is None:
+            ref = out
+            continue
+        for k in FIELDS:
+            assert np.array_equal(out[k], ref[k]), (shape, k)
+    with pytest.raises(EelbmError):
+        g.set_launch(256, 1)
+    run_gpu(cfg, f, 0, "fp64").set_launch(256, 1)
+
+
 def test_advance_zero_and_errors():
     from paper_2409_10399_amd import EelbmError, Lattice
     cfg, f = workloads.periodic_box_2d(nx=16, ny=16)
@@ -256,16 +292,15 @@ def _shift_fields(f, k):
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
-def test_fast_gather_matches_general_bitwise(lattice, storage):
+def test_translation_invariance_bitwise(lattice, storage):
     """A periodic lattice three 64-node x-blocks wide, run twice: once as is
-    and once with its initial fields shifted by one x-block.  Where the step
-    has an interior gather (periodic D3Q19 in 16-bit storage), the interior
-    block's nodes take it in one run and the general (wrap-around) gather in
-    the other; elsewhere every node takes the general gather and the test
-    checks its translation invariance.  Every field must agree bit for bit
-    after the shift, with no tolerance.  The gas fraction is quantised to
-    2^-12 so that its mean, which sets the base of the stored deviations, is
-    exact in any summation order."""
+    and once with its initial fields shifted by one x-block, so that every
+    node sits in another x-block, wavefront and workgroup (and, with staged
+    records, another LDS window position: the wrap-around halo of one run is
+    an interior halo in the other).  Every field must agree bit for bit after
+    the shift, with no tolerance.  The gas fraction is quantised to 2^-12 so
+    that its mean, which sets the base of the stored deviations, is exact in
+    any summation order."""
     if lattice == "D2Q9":
         nx, ny = 192, 16
         cfg = workloads._base("D2Q9", nx=nx, ny=ny, rho_l=10.0, drag="cgw", kappa_I=2e-3, g_hat=1e-5,
@@ -285,15 +320,15 @@ def test_fast_gather_matches_general_bitwise(lattice, storage):
         assert np.array_equal(ra, rb), (k, float(np.max(np.abs(ra - rb))))
 
 
-@pytest.mark.parametrize("storage,tol", [("fp64", 1e-9), ("fp32", 3e-5)])
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-9), ("fp32", 3e-7)])
 @pytest.mark.parametrize("lattice,nx,omega_g,omega_l", [("D2Q9", 11, 1.5, 0.25), ("D3Q19", 7, 1.0, 0.6)])
 def test_poiseuille_walls_exact(lattice, nx, omega_g, omega_l, storage, tol):
     """The GPU's wall rule against the closed form directly: the exact steady
     profile of the BGK scheme with half-way bounce-back walls (both phases,
-    no drag), relative max error 1e-9 in FP64 storage.  FP32 storage: rounding
-    the stored deviations alone leaves the D2Q9 gas profile 2.6e-6 off
-    (test_oracle_scheme.test_fp32_storage_floor_poiseuille), the FP32
-    arithmetic adds about x3; bound 10x the floor, 3e-5."""
+    no drag), relative max error 1e-9 in FP64 storage.  FP32 storage: the
+    storage floor of the residual format is below 2e-7 there
+    (test_oracle_scheme.test_fp32_storage_floor_poiseuille; deviations from
+    w_q would leave 2.6e-6); measured 2e-8 .. 4e-8, bound 3e-7."""
     from closed_forms import poiseuille_case
     cfg, f, up, exact = poiseuille_case(lattice, nx, omega_g, omega_l)
     g = run_gpu(cfg, f, 6000, storage)

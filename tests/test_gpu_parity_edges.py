@@ -115,7 +115,13 @@ def test_spalding_clamp_branches(kind, storage):
             print(f"  clamp {kind} fp32 dp_k {e:.2e}", flush=True)
             assert e <= FP32_TOL
         else:
-            assert np.max(np.abs(rg["dp_k"] - ro["dp_k"])) < 1e-9
+            # dp_k is 0 in exact arithmetic here; rounding the second-order
+            # equilibrium parts (size |u|^2) in FP32 moves the mass of the
+            # uniform flow by less than one unit roundoff of |u|^2 per step
+            usq = float(np.max(np.sum(f["u_g"] ** 2, axis=0)))
+            drift = float(np.max(np.abs(rg["dp_k"] - ro["dp_k"])))
+            print(f"  clamp {kind} fp32 dp_k drift {drift:.2e} (bound {steps * 2.0 ** -24 * usq:.2e})", flush=True)
+            assert drift < steps * 2.0 ** -24 * usq
 
 
 # ---------------------------------------------------- non-finite input

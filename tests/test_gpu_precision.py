@@ -1,17 +1,18 @@
 """Storage precision against the FP64 oracle (per field, rel-L2, after the
-stated number of steps).  Populations are stored as deviations; every
-collision computes in FP32 (FP64 only for the FP64 storage).  The bounds are
-the measured errors with a margin of about 3, and are the stated precision of
-each storage type:
+stated number of steps).  Populations are stored as residuals against the
+equilibrium part of their sender's record (u_g, u_l, alpha_g, eps_g - 1 in
+FP32), so what the storage type rounds is the non-equilibrium and
+second-order part only; every collision computes in FP32 (FP64 only for the
+FP64 storage).  The bounds are the measured errors (MI355X) with a margin of
+about 3, and are the stated precision of each storage type:
 
-* FP16 holds deviations x 2^15 (normal range for |dev| in [2e-9, 2)),
-  relative resolution 2^-11; BF16 holds them unscaled, resolution 2^-8.
-* A field far below the scale of the stored deviations is not resolved by a
-  narrow type: at R = 1000 the liquid velocity is ~1e-3 of the gas velocity,
-  and in periodic boxes delta p_k is 1e-3 (2D box) to 1e-4 (3D column) of the
-  velocity and non-equilibrium parts of the populations -- there even FP32
-  storage leaves delta p_k at rel-L2 ~1e-3 in the column.  Those bounds are
-  stated, not tight.
+* FP32 meets 1e-5 on every field of these cases;
+* FP16 holds the residuals x 2^20 (the moving populations of f_l x 2^26 at
+  R >= 64), relative resolution 2^-11; BF16 holds them unscaled, 2^-8;
+* delta p_k of a column at rest (~1e-4 of the non-equilibrium part of the
+  residuals) is below the resolution of both 16-bit types: its bounds are
+  stated, not tight -- FP32 storage is the choice where the pressure field
+  of such a column matters.
 """
 import numpy as np
 import pytest
@@ -22,15 +23,15 @@ from parity import FIELDS, rel_l2, run_gpu, run_oracle
 pytestmark = pytest.mark.gpu
 
 # measured (MI355X) x ~3, rounded up
-CHANNEL = {  # D2Q9 40x48 channel, R = 1000, CGW, dashpot + lag, 1000 steps
+CHANNEL = {  # D2Q9 40x48 and 320x40 channels, R = 1000, CGW, dashpot + lag, 1000 steps
     "fp32": {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5, "dp_k": 1e-5},
-    "fp16": {"alpha_g": 2e-3, "u_g": 1e-2, "u_l": 1.5e-2, "dp_k": 1e-2},
-    "bf16": {"alpha_g": 0.15, "u_g": 0.2, "u_l": 0.3, "dp_k": 0.25},
+    "fp16": {"alpha_g": 2e-5, "u_g": 5e-4, "u_l": 7e-4, "dp_k": 8e-4},
+    "bf16": {"alpha_g": 5e-4, "u_g": 1.5e-2, "u_l": 3.5e-2, "dp_k": 3e-2},
 }
 COLUMN = {  # D3Q19 32^3 periodic column, R = 1000, blobs on alpha 0.01, 200 steps
-    "fp32": {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5, "dp_k": 1e-2},
-    "fp16": {"alpha_g": 5e-4, "u_g": 5e-3, "u_l": 1.5, "dp_k": 30.0},
-    "bf16": {"alpha_g": 2e-3, "u_g": 0.4, "u_l": 0.4, "dp_k": 60.0},
+    "fp32": {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5, "dp_k": 1e-5},
+    "fp16": {"alpha_g": 1e-5, "u_g": 6e-5, "u_l": 1e-4, "dp_k": 0.7},
+    "bf16": {"alpha_g": 5e-5, "u_g": 7e-4, "u_l": 2e-3, "dp_k": 9.0},
 }
 
 
@@ -46,8 +47,8 @@ def _check(cfg, f, steps, table):
 
 @pytest.mark.parametrize("nx,ny", [(40, 48), (320, 40)])
 def test_storage_precision_channel(nx, ny):
-    """(320 x 40 is five x-blocks wide, so its interior blocks take the fast
-    gather in every storage type; the stated bounds are those of 40 x 48.)"""
+    """(320 x 40 is five x-blocks wide: several workgroups, interior and
+    edge halos of the staged record windows.)"""
     cfg, f = workloads.channel_2d(nx=nx, ny=ny, n_ramp=100.0)
     _check(cfg, f, 1000, CHANNEL)
 
@@ -58,33 +59,31 @@ def test_storage_precision_column():
 
 
 CROP64 = {  # 64^3 crop of the 256^3 column workload (256 blobs), 20 steps
-    "fp32": {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5},  # dp_k: 10 x the FP32 storage floor
-    "fp16": {"alpha_g": 5e-4, "u_g": 3e-3, "u_l": 0.3, "dp_k": 40.0},
-    "bf16": {"alpha_g": 2.5e-3, "u_g": 3.5e-3, "u_l": 2e-2, "dp_k": 40.0},
+    "fp32": {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5, "dp_k": 3e-3},
+    "fp16": {"alpha_g": 1e-5, "u_g": 7e-4, "u_l": 1e-3, "dp_k": 15.0},
+    "bf16": {"alpha_g": 6e-5, "u_g": 3e-3, "u_l": 2.5e-3, "dp_k": 20.0},
 }
 
 
 def test_storage_precision_column_crop64():
     """The 256^3 column's own fields, a 64^3 crop run as a periodic box: every
     storage type against the FP64 oracle, and the 16-bit types against FP32
-    storage (printed).  In FP32, delta p_k (1e-4 of the deviation scale at
-    rest) is bounded by 10 x the storage floor of the oracle with its
-    deviations rounded to FP32 every step (1.0e-2 here; GPU 4.0e-2)."""
-    from storage_floor import fp32_floor
+    storage (printed).  delta p_k starts at 0 and after 20 steps holds only
+    the first acoustic transients (~1e-4 of the residual scale): FP32 storage
+    leaves it at rel-L2 ~1e-3 there (the storage floor of the residual format
+    is below that; the FP32 arithmetic sets it)."""
     cfg, f = workloads.column_3d(n=256, nblobs=256)
     crop = {k: np.ascontiguousarray(v[..., :64, :64, :64]) for k, v in f.items()}
     cfg = dict(cfg, nx=64, ny=64, nz=64)
     steps = 20
     ro = run_oracle(cfg, crop, steps).read()
-    floor = fp32_floor(cfg, crop, steps)
     g = {}
     for storage, tol in CROP64.items():
         g[storage] = run_gpu(cfg, crop, steps, storage).read_all()
         errs = {k: rel_l2(g[storage][k], ro[k]) for k in FIELDS}
         print(f"  {storage} " + " ".join(f"{k}={errs[k]:.2e}" for k in FIELDS), flush=True)
         for k in FIELDS:
-            bound = tol.get(k, 10.0 * floor[k])
-            assert np.isfinite(errs[k]) and errs[k] <= bound, (storage, k, errs[k], bound)
+            assert np.isfinite(errs[k]) and errs[k] <= tol[k], (storage, k, errs[k], tol[k])
     for storage in ("fp16", "bf16"):
         print(f"  {storage} vs fp32 storage " + " ".join(f"{k}={rel_l2(g[storage][k], g['fp32'][k]):.2e}" for k in FIELDS),
               flush=True)
