@@ -46,24 +46,61 @@ def kernel_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def cpu_baseline(steps=20):
-    """The oracle as it stands, single-threaded, on the full 1024x1024 channel
-    for a few steps (a bounded sample of the same workload)."""
+def _cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def cpu_baseline(steps=20, procs=None):
+    """The oracle as it stands on the host cores: a bounded sample of the same
+    workload (the full 1024x1024 channel, `steps` steps), NumPy FP64, one
+    thread per process.  Single core: one process.  All cores: `procs`
+    processes each stepping its own copy at the same time (the oracle is not
+    parallel itself; independent copies are how a CPU runs many such
+    lattices); throughput = all node updates over the span from the first
+    start to the last end of their stepping.  procs defaults to the host's
+    cores, at most 16 (the CPU share of one GPU on these machines)."""
+    model, ncpu = _cpu_info()
+    procs = procs or max(1, min(16, ncpu))
     code = (
         "import sys, time, json; sys.path.insert(0, %r)\n"
         "import workloads\nfrom oracle import Oracle\n"
         "cfg, f = workloads.channel_2d()\n"
         "o = Oracle(cfg, f)\n"
-        "t0 = time.perf_counter(); o.step(%d); dt = time.perf_counter() - t0\n"
-        "print(json.dumps({'dt': dt, 'nodes': cfg['nx'] * cfg['ny']}))\n" % (ROOT, steps))
+        "t0 = time.time(); o.step(%d); t1 = time.time()\n"
+        "print(json.dumps({'t0': t0, 't1': t1, 'nodes': cfg['nx'] * cfg['ny']}))\n" % (ROOT, steps))
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
                HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
-    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
-    if r.returncode != 0:
-        return {"error": r.stderr[-400:]}
-    d = json.loads(r.stdout.strip().splitlines()[-1])
-    return {"value": d["nodes"] * steps / d["dt"] / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"D2Q9 1024x1024 channel, {steps} steps, NumPy FP64, 1 thread ({d['dt']:.1f} s)"}
+
+    def run(n):
+        ps = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                               text=True, env=env) for _ in range(n)]
+        out = []
+        for pr in ps:
+            o, e = pr.communicate(timeout=900)
+            if pr.returncode != 0:
+                raise RuntimeError(e[-400:])
+            out.append(json.loads(o.strip().splitlines()[-1]))
+        span = max(d["t1"] for d in out) - min(d["t0"] for d in out)
+        return sum(d["nodes"] for d in out) * steps / span / 1e6, span
+
+    try:
+        one, dt1 = run(1)
+        allc, dtn = run(procs)
+    except (RuntimeError, subprocess.TimeoutExpired) as e:
+        return {"error": str(e)[-400:]}
+    return {"value": allc, "unit": "MLUPS", "cores": procs, "kind": "oracle",
+            "sample": f"D2Q9 1024x1024 channel, {steps} steps per copy, NumPy FP64, {procs} single-thread "
+                      f"copies at once ({dtn:.1f} s span); one copy alone: {one:.3f} MLUPS ({dt1:.1f} s)",
+            "single_core": one, "host_cpus": ncpu, "cpu_model": model}
 
 
 def main():
