@@ -304,11 +304,26 @@ int eelbm_autotune(eelbm_handle* h, int32_t steps, int32_t force, int32_t* tile_
  * products run on the matrix cores in BF16 with FP32 accumulation. */
 
 /* out = act(conv3x3(in; Wf) + bias), zero padding; act = leaky-ReLU with
- * `slope` if act != 0; bias may be NULL.  One image (H * W * Cin) and the
- * weight copy (9 * Cin * Cout) must each hold fewer than 2^31 values
- * (EELBM_E_PARAM otherwise). */
+ * `slope` if act != 0; bias may be NULL.  The weight copy (9 * Cin * Cout)
+ * must hold fewer than 2^31 values (EELBM_E_PARAM otherwise). */
 int eelbm_cno_conv_fwd(const float* in, int32_t B, int32_t H, int32_t W, int32_t Cin, const uint16_t* wf,
                        const float* bias, int32_t Cout, float* out, int32_t act, float slope, void* stream);
+/* The same convolution of the channel concatenation [src0 | src1] (C0 + C1
+ * input channels; src1 may be NULL with C1 = 0), src0 read with nearest 2x
+ * upsampling from a (B, H/2, W/2, C0) image when up0 != 0: the decoder's
+ * upsampling and skip concatenation fused into the convolution's input (no
+ * intermediate tensors).  H and W must be even when up0 != 0. */
+int eelbm_cno_conv_fwd_cat(const float* src0, int32_t C0, int32_t up0, const float* src1, int32_t C1, int32_t B,
+                           int32_t H, int32_t W, const uint16_t* wf, const float* bias, int32_t Cout, float* out,
+                           int32_t act, float slope, void* stream);
+/* Tile of the forward and input-gradient convolutions, process-wide: mt
+ * M-tiles of 16 pixels per wavefront (1, 2 or 4) x nt N-tiles of 16 output
+ * channels per workgroup (1..4); (0, 0) restores the automatic choice (the
+ * most operand reuse that still gives about four workgroups per compute
+ * unit).  For tests and tuning.  A set tile applies to every later call; a
+ * call whose Cout / 16 nt does not divide then returns EELBM_E_PARAM.
+ * EELBM_E_PARAM for other values. */
+int eelbm_cno_conv_set_tile(int32_t mt, int32_t nt);
 /* din = gradient of the convolution wrt its input, given dout (the gradient
  * wrt the pre-activation output); the size limits of eelbm_cno_conv_fwd apply
  * with the roles of Cin and Cout exchanged. */
@@ -316,7 +331,11 @@ int eelbm_cno_conv_bwd_data(const float* dout, int32_t B, int32_t H, int32_t W, 
                             int32_t Cin, float* din, void* stream);
 /* dw[tap][ci][co] += sum over pixels of in(shifted) * dout; dbias[co] += sum
  * of dout (dbias may be NULL).  Accumulates: zero them first (eelbm_cno_fill).
- * Cout <= 256; B * H * W below 2^31 - 2048 pixels (EELBM_E_PARAM otherwise). */
+ * Deterministic: per-chunk partial sums are added in chunk order (no
+ * atomics), in a partial-sum workspace the library allocates per device on
+ * first use and keeps (grown when a larger layer needs it; calls that
+ * overlap on one device from different streams race on it).
+ * Cout <= 256; B * H * W below 2^31 - 4096 pixels (EELBM_E_PARAM otherwise). */
 int eelbm_cno_conv_bwd_weight(const float* in, const float* dout, int32_t B, int32_t H, int32_t W, int32_t Cin,
                               int32_t Cout, float* dw, float* dbias, void* stream);
 /* dx = dy where y > 0, slope * dy elsewhere (y: the leaky-ReLU output). */

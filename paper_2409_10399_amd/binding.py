@@ -75,6 +75,9 @@ SYMBOLS = {
     "eelbm_autotune": (c_int, [c_void_p, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]),
     "eelbm_reinit_fields": (c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
     # learned surrogate kernels (device pointers, NHWC FP32)
+    "eelbm_cno_conv_fwd_cat": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_int32,
+                                       c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.c_float, c_void_p]),
+    "eelbm_cno_conv_set_tile": (c_int, [c_int32, c_int32]),
     "eelbm_cno_conv_fwd": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int32,
                                    c_void_p, c_int32, ctypes.c_float, c_void_p]),
     "eelbm_cno_conv_bwd_data": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,

@@ -17,6 +17,8 @@
 // so that the four K-consecutive values a lane needs are adjacent.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <mutex>
 
@@ -51,92 +53,182 @@ __device__ __forceinline__ f32x4 mfma(const s16x4& a, const s16x4& b, const f32x
 // --------------------------------------------------------------- forward
 // out[b, y, x, co] = bias[co] + sum_{tap, ci} in[b, y + dy, x + dx, ci] Wf[co][tap][ci]
 // (zero padding), then leaky-ReLU with slope `slope` if act != 0.
-// A wavefront owns MT x 16 consecutive pixels of one image row (MT M-tiles)
-// and NT output tiles of 16 channels: each loaded weight fragment feeds MT
-// matrix-core products and each loaded pixel fragment NT.
-// Grid: x = pixel groups of 16 MT (rows padded), y = groups of NT output tiles.
+//
+// A workgroup of four wavefronts owns kRows output rows (one per wavefront)
+// x 16 MT pixels x 16 NT output channels.  The K loop runs over chunks of 32
+// input channels; for each chunk the workgroup stages in LDS, as BF16,
+//   * the input window: kRows + 2 rows x 16 MT + 2 pixels x 32 channels (zero
+//     outside the image and beyond the input channels),
+//   * the weights: 9 taps x 16 NT output channels x 32 input channels,
+// and every wavefront takes its operands of the nine taps from there (one
+// 16-byte LDS read per M-tile and per N-tile and tap) into the 16x16x32 BF16
+// matrix-core instruction of gfx950.  All global loads of a chunk are issued
+// together, and those of the next chunk are in flight while the current one
+// is multiplied (one LDS buffer, refilled between two barriers).  Operand
+// layout of v_mfma_f32_16x16x32_bf16 (lane l, element t):
+//   A[m = l % 16][k = 8 (l / 16) + t] (t < 8),  B[k = 8 (l / 16) + t][n = l % 16] (t < 8),
+//   D[m = 4 (l / 16) + t][n = l % 16] (t < 4).
+// The input may be the concatenation [src0 | src1] along channels, and src0
+// may be read with nearest 2x upsampling from an image of half the size (the
+// decoder's upsampling and skip concatenation, fused into the load).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f32x4 mfma32(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+constexpr int kRows = 4;  // output rows of a workgroup, one per wavefront
+constexpr int kKc = 32;   // input channels per staged chunk
+constexpr int kPix = 40;  // LDS stride of one staged pixel or weight row in BF16 values (32 + 8 padding: 80 bytes)
+
 template <int MT, int NT>
-__global__ void __launch_bounds__(64) k_conv_fwd(const float* __restrict__ in, int B, int H, int W, int Cin,
-                                                const unsigned short* __restrict__ wf, const float* __restrict__ bias,
-                                                int Cout, float* __restrict__ out, int act, float slope) {
-    (void)B;  // the grid covers the B * H image rows
-    const int lane = threadIdx.x;
-    const int gw = (W + 16 * MT - 1) / (16 * MT);
-    const long long grp = blockIdx.x;
-    const int xg = (int)(grp % gw);
-    const long long by = grp / gw;  // b * H + y
-    const int y = (int)(by % H);
-    const int b = (int)(by / H);
-    const int x0 = xg * 16 * MT + (lane & 15);  // pixel of this lane's A row in M-tile 0
-    const int kq = 4 * (lane >> 4);              // K offset of this lane within a 16-chunk
-    const int n0 = blockIdx.y * NT * 16;        // the host launches Cout / (16 NT) tiles exactly
+struct ConvTile {
+    static constexpr int TW = 16 * MT;                    // output pixels of a row in the tile
+    static constexpr int LW = TW + 2;                     // staged pixels of a row
+    static constexpr int kA = (kRows + 2) * LW * (kKc / 4);  // 4-channel groups of the input window
+    static constexpr int kAi = (kA + 255) / 256;          // ... per thread
+    static constexpr int kB = 9 * 16 * NT * (kKc / 8);    // 8-channel groups of the weights
+    static constexpr int kBi = (kB + 255) / 256;
+    static constexpr int kLdsA = (kRows + 2) * LW * kPix;  // BF16 values
+    static constexpr int kLdsB = 9 * 16 * NT * kPix;
+};
+
+template <int MT, int NT>
+__global__ void __launch_bounds__(256) k_conv2(const float* __restrict__ src0, int C0, int up0,
+                                              const float* __restrict__ src1, int C1, int B, int H, int W,
+                                              const unsigned short* __restrict__ wf, const float* __restrict__ bias,
+                                              int Cout, float* __restrict__ out, int act, float slope) {
+    using T = ConvTile<MT, NT>;
+    constexpr int LW = T::LW;
+    __shared__ __attribute__((aligned(16))) unsigned short atile[T::kLdsA];
+    __shared__ __attribute__((aligned(16))) unsigned short btile[T::kLdsB];
+    const int Cin = C0 + C1;
     const int K = 9 * Cin;
-    const int nc = Cin / 16;  // 16-channel chunks per tap
-    f32x4 acc[MT][NT];
-    float bc[NT];
+    const int nch = (Cin + kKc - 1) / kKc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gx = (W + T::TW - 1) / T::TW, gy = (H + kRows - 1) / kRows;
+    const int ntiles = B * gx * gy;  // < 2^24 (host check)
+    const int n0 = blockIdx.y * 16 * NT;  // the host launches Cout / (16 NT) groups exactly
+    const int Hs = up0 ? H / 2 : H, Ws = up0 ? W / 2 : W;
+    const int kh = 8 * (lane >> 4);  // this lane's K offset within a chunk
+
+    f32x4 av[T::kAi];
+    u32x4 bv[T::kBi];
+    // issue every global load of chunk c0 of tile `tile` (the values land in
+    // av and, if withb, bv)
+    auto load = [&](int tile, int c0, bool withb) {
+        const int xt = tile % gx, r = tile / gx;
+        const int yt = r % gy, b = r / gy;
+        const int x0 = xt * T::TW, y0 = yt * kRows;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        bc[j] = bias ? bias[n0 + j * 16 + (lane & 15)] : 0.f;
-#pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    const unsigned short* wrow = wf + (long long)(n0 + (lane & 15)) * K + kq;
-    const float* img = in + (long long)b * H * W * Cin + kq;  // H * W * Cin < 2^31 (host check)
-    // fragments of one (tap, chunk) step: loads always address a valid pixel
-    // (the image's first one when the tap falls outside), the value is
-    // zeroed after the load; the next step's loads are issued before this
-    // step's products
-    f32x4 av[MT];
-    u16x4 bv[NT];
-    bool ok[MT];
-    auto load = [&](int tap, int c0) {
-        const int yy = y + tap / 3 - 1;
-        const bool oky = (unsigned)yy < (unsigned)H;
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            const int xx = x0 + 16 * m + tap % 3 - 1;
-            ok[m] = oky & ((unsigned)xx < (unsigned)W);
-            const int pix = ok[m] ? yy * W + xx : 0;
-            av[m] = *reinterpret_cast<const f32x4*>(img + (pix * Cin + c0));
-        }
-        const int k = tap * Cin + c0;
-#pragma unroll
-        for (int j = 0; j < NT; ++j) bv[j] = *reinterpret_cast<const u16x4*>(wrow + (j * 16 * K + k));
-    };
-    int tap = 0, ch = 0;
-    load(0, 0);
-    for (int it = 0; it < 9 * nc; ++it) {
-        s16x4 a[MT], bw[NT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            const s16x4 h = pack4(av[m]);
-            a[m] = ok[m] ? h : s16x4{0, 0, 0, 0};
-        }
-#pragma unroll
-        for (int j = 0; j < NT; ++j) bw[j] = __builtin_bit_cast(s16x4, bv[j]);
-        if (++ch == nc) {
-            ch = 0;
-            ++tap;
-        }
-        if (tap < 9) load(tap, ch * 16);
-#pragma unroll
-        for (int j = 0; j < NT; ++j)
-#pragma unroll
-            for (int m = 0; m < MT; ++m) acc[m][j] = mfma(a[m], bw[j], acc[m][j]);
-    }
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const int co = n0 + j * 16 + (lane & 15);
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int px = xg * 16 * MT + 16 * m + 4 * (lane >> 4) + t;
-                float v = acc[m][j][t] + bc[j];
-                v = (act && v < 0.f) ? slope * v : v;
-                if (px < W) out[(((long long)b * H + y) * W + px) * Cout + co] = v;
+        for (int i = 0; i < T::kAi; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            const int g = e & 7, pix = e >> 3;
+            const int lx = pix % LW, ly = pix / LW;
+            const int yy = y0 - 1 + ly, xx = x0 - 1 + lx;
+            const int c = c0 + 4 * g;
+            av[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (e < T::kA && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W && c < Cin) {
+                if (c < C0) {
+                    const long long q = up0 ? ((long long)b * Hs + (yy >> 1)) * Ws + (xx >> 1)
+                                            : ((long long)b * H + yy) * W + xx;
+                    av[i] = *reinterpret_cast<const f32x4*>(src0 + q * C0 + c);
+                } else {
+                    const long long q = ((long long)b * H + yy) * W + xx;
+                    av[i] = *reinterpret_cast<const f32x4*>(src1 + q * C1 + (c - C0));
+                }
             }
         }
+        if (!withb) return;
+#pragma unroll
+        for (int i = 0; i < T::kBi; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            const int g = e & 3, rr = e >> 2;  // rr = tap * 16 NT + column
+            const int tap = rr / (16 * NT), col = rr % (16 * NT);
+            const int k = c0 + 8 * g;
+            bv[i] = u32x4{0u, 0u, 0u, 0u};
+            if (e < T::kB && k < Cin)
+                bv[i] = *reinterpret_cast<const u32x4*>(wf + (long long)(n0 + col) * K + tap * Cin + k);
+        }
+    };
+    // write the loaded chunk to LDS
+    auto store = [&](bool withb) {
+#pragma unroll
+        for (int i = 0; i < T::kAi; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            if (e < T::kA) *reinterpret_cast<s16x4*>(atile + (e >> 3) * kPix + 4 * (e & 7)) = pack4(av[i]);
+        }
+        if (!withb) return;
+#pragma unroll
+        for (int i = 0; i < T::kBi; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            if (e < T::kB) *reinterpret_cast<u32x4*>(btile + (e >> 2) * kPix + 8 * (e & 3)) = bv[i];
+        }
+    };
+
+    // Each workgroup takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the
+    // loads of the next (tile, chunk) are in flight while the current one is
+    // multiplied.  With a single chunk the weights stay in LDS for all tiles.
+    int tile = blockIdx.x, ch = 0;
+    if (tile >= ntiles) return;
+    load(tile, 0, true);
+    f32x4 acc[MT][NT];
+    for (bool first = true;; first = false) {
+        if (ch == 0) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+        __syncthreads();  // the previous chunk's LDS reads are done
+        store(nch > 1 || first);
+        __syncthreads();
+        int ntile = tile, nc = ch + 1;
+        if (nc == nch) {
+            nc = 0;
+            ntile += gridDim.x;
+        }
+        const bool more = ntile < ntiles;
+        if (more) load(ntile, nc * kKc, nch > 1);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+            bf16x8 a[MT], bw[NT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                a[m] = *reinterpret_cast<const bf16x8*>(atile + ((wave + dy) * LW + 16 * m + (lane & 15) + dx) * kPix + kh);
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                bw[j] = *reinterpret_cast<const bf16x8*>(btile + (tap * 16 * NT + 16 * j + (lane & 15)) * kPix + kh);
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+#pragma unroll
+                for (int m = 0; m < MT; ++m) acc[m][j] = mfma32(a[m], bw[j], acc[m][j]);
+        }
+        if (ch == nch - 1) {
+            const int xt = tile % gx, r = tile / gx;
+            const int yt = r % gy, b = r / gy;
+            const int y = yt * kRows + wave;
+            if (y < H) {
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    const int co = n0 + 16 * j + (lane & 15);
+                    const float bc = bias ? bias[co] : 0.f;
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int px = xt * T::TW + 16 * m + 4 * (lane >> 4) + t;
+                            float v = acc[m][j][t] + bc;
+                            v = (act && v < 0.f) ? slope * v : v;
+                            if (px < W) out[(((long long)b * H + y) * W + px) * Cout + co] = v;
+                        }
+                    }
+                }
+            }
+        }
+        if (!more) break;
+        tile = ntile;
+        ch = nc;
     }
 }
 
@@ -144,15 +236,16 @@ __global__ void __launch_bounds__(64) k_conv_fwd(const float* __restrict__ in, i
 // din[b, y, x, ci] = sum_{tap, co} dout[b, y - dy, x - dx, co] W[tap][ci][co]
 //                  = sum_{tap', co} dout[b, y + dy', x + dx', co] Wd[ci][tap'][co]
 // with the taps reversed (tap' = 8 - tap, dy' = -dy, dx' = -dx): a forward
-// convolution of dout with Wd, run by k_conv_fwd.
+// convolution of dout with Wd, run by k_conv2.
 
 // ---------------------------------------------------- gradient wrt weights
-// dW[tap][ci][co] += sum_p in[p + d_tap][ci] dout[p][co] over this
-// workgroup's chunk of `chunk` pixels (M = (tap, ci), N = co, K = pixels);
-// one wavefront per 16 x 16 tile of dW, partial sums added atomically.
+// part[z][tap][ci][co] = sum_p in[p + d_tap][ci] dout[p][co] over chunk z of
+// `chunk` pixels (M = (tap, ci), N = co, K = pixels); one wavefront per
+// 16 x 16 tile of dW and chunk.  k_sum_parts then adds the chunks in their
+// order, so the gradient does not depend on the launch (no atomics).
 __global__ void __launch_bounds__(64) k_conv_bwd_weight(const float* __restrict__ in, const float* __restrict__ dout,
                                                        int B, int H, int W, int Cin, int Cout, int chunk,
-                                                       float* __restrict__ dw) {
+                                                       float* __restrict__ part) {
     const int lane = threadIdx.x;
     const int mt = blockIdx.x;  // M tile over 9 * Cin
     const int nt = blockIdx.y;  // N tile over Cout
@@ -200,21 +293,32 @@ __global__ void __launch_bounds__(64) k_conv_bwd_weight(const float* __restrict_
         }
         acc = mfma(pack4(av), pack4(bv), acc);
     }
+    float* pz = part + (long long)blockIdx.z * 9 * Cin * Cout;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int mm = mt * 16 + 4 * (lane >> 4) + t;  // row of D
-        atomicAdd(dw + (long long)mm * Cout + co, acc[t]);
+        pz[(long long)mm * Cout + co] = acc[t];
     }
 }
 
-__global__ void k_bias_grad(const float* __restrict__ dout, long long P, int C, float* __restrict__ db) {
-    // one workgroup per 256-pixel chunk, one thread per channel (C <= 256)
+__global__ void k_bias_grad(const float* __restrict__ dout, long long P, int C, float* __restrict__ part) {
+    // one workgroup per 256-pixel chunk, one thread per channel (C <= 256):
+    // part[chunk][c]
     const int c = threadIdx.x;
     if (c >= C) return;
     const long long p0 = (long long)blockIdx.x * 256;
     float s = 0.f;
     for (long long p = p0; p < p0 + 256 && p < P; ++p) s += dout[p * C + c];
-    atomicAdd(db + c, s);
+    part[(long long)blockIdx.x * C + c] = s;
+}
+
+// acc[i] += sum_z part[z][i], z in order
+__global__ void k_sum_parts(const float* __restrict__ part, int nz, long long n, float* __restrict__ acc) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int z = 0; z < nz; ++z) s += part[(long long)z * n + i];
+        acc[i] += s;
+    }
 }
 
 __global__ void k_act_bwd(const float* __restrict__ y, const float* __restrict__ dy, long long n, float slope,
@@ -424,27 +528,102 @@ using namespace cno;
 namespace {
 int last_rc(hipError_t e) { return e == hipSuccess ? EELBM_OK : EELBM_E_HIP; }
 
-// forward tiling: MT M-tiles of 16 pixels (up to 4, no more than a row holds)
-// and NT <= 4 output tiles per wavefront, NT dividing the output tiles
-constexpr int kFwdMaxNT = 4;
-
-template <int MT, int NT>
-void fwd_mn(const float* in, int B, int H, int W, int Cin, const unsigned short* wf, const float* bias, int Cout,
-            float* out, int act, float slope, hipStream_t s) {
-    const dim3 g((unsigned)((long long)B * H * ((W + 16 * MT - 1) / (16 * MT))), (unsigned)(Cout / (16 * NT)));
-    hipLaunchKernelGGL((k_conv_fwd<MT, NT>), g, dim3(64), 0, s, in, B, H, W, Cin, wf, bias, Cout, out, act, slope);
+// compute units of the current device (cached per device; 256 if unknown)
+std::atomic<int> g_cus[64];
+int cu_count() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = g_cus[dev].load();
+    if (n <= 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        g_cus[dev].store(n);
+    }
+    return n;
 }
 
-template <int MT>
-bool fwd_m(int nt, const float* in, int B, int H, int W, int Cin, const unsigned short* wf, const float* bias,
-           int Cout, float* out, int act, float slope, hipStream_t s) {
-    switch (nt) {
-        case 1: fwd_mn<MT, 1>(in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s); return true;
-        case 2: fwd_mn<MT, 2>(in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s); return true;
-        case 3: fwd_mn<MT, 3>(in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s); return true;
-        case 4: fwd_mn<MT, 4>(in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s); return true;
+// forward tiling: MT M-tiles of 16 pixels per wavefront (1, 2 or 4) and NT
+// output tiles of 16 channels per workgroup (1 to 4, dividing Cout / 16)
+template <int MT, int NT>
+void conv2_mn(const float* src0, int C0, int up0, const float* src1, int C1, int B, int H, int W,
+              const unsigned short* wf, const float* bias, int Cout, float* out, int act, float slope, hipStream_t s) {
+    // at most as many workgroups as fit on the chip at once (LDS-bound), each
+    // looping over its share of the tiles
+    const long long tiles = (long long)B * ((H + kRows - 1) / kRows) * ((W + 16 * MT - 1) / (16 * MT));
+    const int ngroups = Cout / (16 * NT);
+    static std::atomic<int> per_cu{0};  // workgroups of this kernel one compute unit holds (LDS, registers)
+    int pc = per_cu.load();
+    if (pc <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, reinterpret_cast<const void*>(&k_conv2<MT, NT>), 256,
+                                                         0) != hipSuccess ||
+            pc <= 0)
+            pc = 1;
+        per_cu.store(pc);
     }
-    return false;
+    const long long resident = std::max(1ll, (long long)cu_count() * pc / ngroups);
+    const dim3 g((unsigned)std::min(tiles, resident), (unsigned)ngroups);
+    hipLaunchKernelGGL((k_conv2<MT, NT>), g, dim3(256), 0, s, src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out,
+                       act, slope);
+}
+template <int MT>
+void conv2_m(int nt, const float* src0, int C0, int up0, const float* src1, int C1, int B, int H, int W,
+             const unsigned short* wf, const float* bias, int Cout, float* out, int act, float slope, hipStream_t s) {
+    switch (nt) {
+        case 1: conv2_mn<MT, 1>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
+        case 2: conv2_mn<MT, 2>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
+        case 3: conv2_mn<MT, 3>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
+        default: conv2_mn<MT, 4>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
+    }
+}
+// The tile with the most operand reuse (largest MT x NT) among those that
+// still give at least kMinGroups workgroups (four per compute unit), else the
+// one with the most workgroups: the small images of the inner levels need
+// many small tiles to keep the chip busy through their long K loops.
+constexpr long long kMinGroups = 1024;
+std::atomic<int> g_tile_mt{0}, g_tile_nt{0};  // eelbm_cno_conv_set_tile; 0: automatic
+void conv2_tile(int B, int H, int W, int Cout, int* mt, int* nt) {
+    static const int order[12][2] = {{4, 4}, {4, 3}, {4, 2}, {2, 4}, {2, 3}, {4, 1},
+                                     {2, 2}, {1, 4}, {1, 3}, {2, 1}, {1, 2}, {1, 1}};
+    long long best = -1;
+    for (const auto& c : order) {
+        const int m = c[0], n = c[1];
+        if ((Cout / 16) % n != 0 || (m > 1 && 16 * m > W)) continue;
+        const long long g = (long long)B * ((H + kRows - 1) / kRows) * ((W + 16 * m - 1) / (16 * m)) * (Cout / (16 * n));
+        if (g >= kMinGroups) {
+            *mt = m;
+            *nt = n;
+            return;
+        }
+        if (g > best) {
+            best = g;
+            *mt = m;
+            *nt = n;
+        }
+    }
+}
+
+// Partial-sum workspace of the weight and bias gradients, held by the library
+// per device (grown on demand, kept until the process ends): calls on one
+// device and stream run in order and reuse it; calls that overlap on one
+// device from different streams race on it.
+constexpr long long kWgradParts = 4096;  // tile-chunks of 16 x 16 weights
+std::mutex g_ws_mu;
+float* g_ws[64] = {};
+size_t g_ws_n[64] = {};
+int workspace_for_current_device(size_t n, float** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return EELBM_E_HIP;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if (g_ws_n[dev] < n) {
+        // a kernel still in flight may use the old one
+        if (g_ws[dev] && (hipDeviceSynchronize() != hipSuccess || hipFree(g_ws[dev]) != hipSuccess))
+            return EELBM_E_HIP;
+        g_ws[dev] = nullptr;
+        g_ws_n[dev] = 0;
+        if (hipMalloc(reinterpret_cast<void**>(&g_ws[dev]), n * sizeof(float)) != hipSuccess) return EELBM_E_HIP;
+        g_ws_n[dev] = n;
+    }
+    *out = g_ws[dev];
+    return EELBM_OK;
 }
 
 bool shape_ok(int B, int H, int W, int Cin, int Cout) {
@@ -455,21 +634,44 @@ bool shape_ok(int B, int H, int W, int Cin, int Cout) {
 
 extern "C" {
 
-int eelbm_cno_conv_fwd(const float* in, int32_t B, int32_t H, int32_t W, int32_t Cin, const uint16_t* wf,
-                       const float* bias, int32_t Cout, float* out, int32_t act, float slope, void* stream) {
-    if (!in || !wf || !out || !shape_ok(B, H, W, Cin, Cout)) return EELBM_E_PARAM;
-    int nt = 1;
-    for (int d = 1; d <= kFwdMaxNT; ++d)
-        if ((Cout / 16) % d == 0) nt = d;
-    if ((long long)B * H * ((W + 15) / 16) >= (1ll << 32) || (long long)H * W * Cin >= (1ll << 31) ||
+int eelbm_cno_conv_fwd_cat(const float* src0, int32_t C0, int32_t up0, const float* src1, int32_t C1, int32_t B,
+                           int32_t H, int32_t W, const uint16_t* wf, const float* bias, int32_t Cout, float* out,
+                           int32_t act, float slope, void* stream) {
+    if (!src0 || !wf || !out || C0 <= 0 || C0 % 16 != 0 || C1 < 0 || C1 % 16 != 0 || (C1 > 0 && !src1) ||
+        !shape_ok(B, H, W, C0 + C1, Cout))
+        return EELBM_E_PARAM;
+    if (up0 && (H % 2 != 0 || W % 2 != 0)) return EELBM_E_PARAM;
+    const int Cin = C0 + C1;
+    // workgroups of 256 threads along x: their threads must number < 2^32
+    if ((long long)B * ((H + kRows - 1) / kRows) * ((W + 15) / 16) >= (1ll << 24) ||
         (long long)Cout * 9 * Cin >= (1ll << 31))
         return EELBM_E_PARAM;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const bool ok = W >= 64   ? fwd_m<4>(nt, in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s)
-                    : W >= 32 ? fwd_m<2>(nt, in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s)
-                              : fwd_m<1>(nt, in, B, H, W, Cin, wf, bias, Cout, out, act, slope, s);
-    if (!ok) return EELBM_E_PARAM;
+    const unsigned short* w = reinterpret_cast<const unsigned short*>(wf);
+    int mt = g_tile_mt.load(), nt = g_tile_nt.load();
+    if (mt == 0)
+        conv2_tile(B, H, W, Cout, &mt, &nt);
+    else if ((Cout / 16) % nt != 0)
+        return EELBM_E_PARAM;
+    if (mt == 4)
+        conv2_m<4>(nt, src0, C0, up0, src1, C1, B, H, W, w, bias, Cout, out, act, slope, s);
+    else if (mt == 2)
+        conv2_m<2>(nt, src0, C0, up0, src1, C1, B, H, W, w, bias, Cout, out, act, slope, s);
+    else
+        conv2_m<1>(nt, src0, C0, up0, src1, C1, B, H, W, w, bias, Cout, out, act, slope, s);
     return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_conv_set_tile(int32_t mt, int32_t nt) {
+    if (!((mt == 0 && nt == 0) || ((mt == 1 || mt == 2 || mt == 4) && nt >= 1 && nt <= 4))) return EELBM_E_PARAM;
+    g_tile_nt.store(nt);
+    g_tile_mt.store(mt);
+    return EELBM_OK;
+}
+
+int eelbm_cno_conv_fwd(const float* in, int32_t B, int32_t H, int32_t W, int32_t Cin, const uint16_t* wf,
+                       const float* bias, int32_t Cout, float* out, int32_t act, float slope, void* stream) {
+    return eelbm_cno_conv_fwd_cat(in, Cin, 0, nullptr, 0, B, H, W, wf, bias, Cout, out, act, slope, stream);
 }
 
 int eelbm_cno_conv_bwd_data(const float* dout, int32_t B, int32_t H, int32_t W, int32_t Cout, const uint16_t* wd,
@@ -485,15 +687,33 @@ int eelbm_cno_conv_bwd_weight(const float* in, const float* dout, int32_t B, int
     if (!in || !dout || !dw || !shape_ok(B, H, W, Cin, Cout) || Cout > 256) return EELBM_E_PARAM;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const long long P = (long long)B * H * W;
-    const int chunk = 2048;
-    const long long nk = (P + chunk - 1) / chunk;
-    if (nk > 65535 || P + chunk >= (1ll << 31)) return EELBM_E_PARAM;
+    if (P >= (1ll << 31) - 4096) return EELBM_E_PARAM;
+    // pixel chunks: enough workgroups to fill the GPU, at most kWgradParts
+    // tile-chunks in the workspace
+    const long long tiles = (long long)(9 * Cin / 16) * (Cout / 16);
+    long long nk = std::max(1ll, std::min((P + 255) / 256, kWgradParts / tiles));
+    const int chunk = (int)(((P + nk - 1) / nk + 15) / 16 * 16);
+    nk = (P + chunk - 1) / chunk;
+    const long long nw = 9ll * Cin * Cout;
+    const long long nb = (P + 255) / 256;
+    float* ws = nullptr;
+    int rc = workspace_for_current_device((size_t)std::max(nk * nw, dbias ? nb * Cout : 0ll), &ws);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_conv_bwd_weight, dim3((unsigned)(9 * Cin / 16), (unsigned)(Cout / 16), (unsigned)nk),
-                       dim3(64), 0, s, in, dout, B, H, W, Cin, Cout, chunk, dw);
+                       dim3(64), 0, s, in, dout, B, H, W, Cin, Cout, chunk, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return EELBM_E_HIP;
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)std::min(4096ll, (nw + 255) / 256)), dim3(256), 0, s, ws, (int)nk,
+                       nw, dw);
+    e = hipGetLastError();
+    if (e != hipSuccess) return EELBM_E_HIP;
     if (dbias) {
-        hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, dout, P, Cout, dbias);
+        // the bias partials reuse the workspace once the weight sums have read it (same stream)
+        hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)nb), dim3(256), 0, s, dout, P, Cout, ws);
+        e = hipGetLastError();
+        if (e != hipSuccess) return EELBM_E_HIP;
+        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)std::min(4096ll, ((long long)Cout + 255) / 256)), dim3(256), 0,
+                           s, ws, (int)nb, (long long)Cout, dbias);
         e = hipGetLastError();
     }
     return last_rc(e);

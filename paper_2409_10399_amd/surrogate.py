@@ -115,10 +115,13 @@ class CNO:
         _check(lib().eelbm_cno_conv_fwd(_p(x), B, H, W, ci, _p(self.wf[li]), _p(self.b[li]), out.shape[3], _p(out),
                                         int(act), self.slope, _stream()))
 
-    def forward(self, x):
+    def forward(self, x, keep=True):
         """x: (B, H, W, cin) FP32 contiguous device tensor (H, W divisible by
         2^(levels-1)); returns (B, H, W, cout) (the first cout_used channels
-        are the output)."""
+        are the output).  The decoder's upsampling and skip concatenation are
+        fused into the input loads of its convolutions; keep=True also
+        materialises the upsampled and concatenated tensors, which backward()
+        needs (inference passes keep=False)."""
         L, st = lib(), _stream()
         B, H, W, _ = x.shape
         nl, wd = len(self.widths), self.widths
@@ -136,17 +139,19 @@ class CNO:
                 h = p
         for k in range(nl - 2, -1, -1):
             Hk, Wk = H >> k, W >> k
-            u = self._buf(f"u{k}", (B, Hk, Wk, wd[k + 1]))
-            _check(L.eelbm_cno_up(_p(h), B, Hk // 2, Wk // 2, wd[k + 1], _p(u), 0, st))
+            skip = self._buf(f"e{k}_1", (B, Hk, Wk, wd[k]))
             d1 = self._buf(f"d{k}_1", (B, Hk, Wk, wd[k]))
-            self._conv(u, li, d1, True)
-            li += 1
-            cat = self._buf(f"c{k}", (B, Hk, Wk, 2 * wd[k]))
-            _check(L.eelbm_cno_concat(_p(d1), wd[k], _p(self._buf(f"e{k}_1", (B, Hk, Wk, wd[k]))), wd[k],
-                                      B * Hk * Wk, _p(cat), st))
+            _check(L.eelbm_cno_conv_fwd_cat(_p(h), wd[k + 1], 1, None, 0, B, Hk, Wk, _p(self.wf[li]), _p(self.b[li]),
+                                            wd[k], _p(d1), 1, self.slope, st))
             d2 = self._buf(f"d{k}_2", (B, Hk, Wk, wd[k]))
-            self._conv(cat, li, d2, True)
-            h, li = d2, li + 1
+            _check(L.eelbm_cno_conv_fwd_cat(_p(d1), wd[k], 0, _p(skip), wd[k], B, Hk, Wk, _p(self.wf[li + 1]),
+                                            _p(self.b[li + 1]), wd[k], _p(d2), 1, self.slope, st))
+            if keep:
+                u = self._buf(f"u{k}", (B, Hk, Wk, wd[k + 1]))
+                _check(L.eelbm_cno_up(_p(h), B, Hk // 2, Wk // 2, wd[k + 1], _p(u), 0, st))
+                cat = self._buf(f"c{k}", (B, Hk, Wk, 2 * wd[k]))
+                _check(L.eelbm_cno_concat(_p(d1), wd[k], _p(skip), wd[k], B * Hk * Wk, _p(cat), st))
+            h, li = d2, li + 2
         out = self._buf("out", (B, H, W, self.cout))
         self._conv(h, li, out, False)
         self._shape = (B, H, W)
@@ -278,13 +283,13 @@ def _time_forward():
     net = CNO(9, 6, [int(w) for w in a.widths.split(",")], seed=0)
     x = torch.randn(a.batch, a.grid, a.grid, net.cin, device="cuda")
     for _ in range(3):
-        net.forward(x)
+        net.forward(x, keep=False)
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(st)
     for _ in range(a.reps):
-        net.forward(x)
+        net.forward(x, keep=False)
     e1.record(st)
     torch.cuda.synchronize()
     print(json.dumps({"widths": net.widths, "params": net.n_params, "batch": a.batch, "grid": a.grid,

@@ -208,7 +208,8 @@ def train(net, snaps, cond, norm, lag, epochs, bsz, lr, log, keep, noise=0.0, pu
             c = torch.stack([cond[i] for _, i in idx]).contiguous()
             if push:
                 fm = torch.stack([snaps[s - lag, i] for s, i in idx]).contiguous()
-                f0 = apply_output(fm, net.forward(pack_input(fm, norm.mean, norm.inv, c, net.cin)), norm.dscale)
+                f0 = apply_output(fm, net.forward(pack_input(fm, norm.mean, norm.inv, c, net.cin), keep=False),
+                                  norm.dscale)
             else:
                 f0 = torch.stack([snaps[s, i] for s, i in idx]).contiguous()
             x = pack_input(f0, norm.mean, norm.inv, c, net.cin)
@@ -256,7 +257,7 @@ def rollout(net, lats, inst, cond, norm, t0, jumps, jump, defect_max, check_ever
     defects = []
     for j in range(jumps):
         x = pack_input(f, norm.mean, norm.inv, cond, net.cin)
-        pred = apply_output(f, net.forward(x), norm.dscale)
+        pred = apply_output(f, net.forward(x, keep=False), norm.dscale)
         if project:
             conserve(f, pred, jump, chi)
         dfc = defect(f, pred, jump, chi)
@@ -390,7 +391,7 @@ def main():
     for lat, blob in zip(run_lats, blobs):
         lat.load(blob)
     del runb
-    net.forward(torch.zeros((len(run_lats), a.grid, a.grid, net.cin), device="cuda"))  # warm-up
+    net.forward(torch.zeros((len(run_lats), a.grid, a.grid, net.cin), device="cuda"), keep=False)  # warm-up
     torch.cuda.synchronize()
     e0.record()
     t_wall = time.time()

@@ -68,6 +68,106 @@ def test_conv_kernels_match_reference(shape):
     assert rel(host(gb), g.astype(np.float64).sum(axis=(0, 1, 2))) < 1e-5
 
 
+@pytest.mark.parametrize("case", [(2, 8, 16, 96, 48, 48, 1), (1, 3, 10, 48, 32, 32, 1), (2, 16, 36, 32, 16, 32, 0),
+                                  (1, 4, 40, 192, 96, 96, 1)])
+def test_fused_upsample_concat_conv_matches_reference(case):
+    """eelbm_cno_conv_fwd_cat: src0 read with nearest 2x upsampling (or as is)
+    and concatenated with src1 along channels, in the convolution's loads,
+    against the reference convolution of the explicitly built input."""
+    import torch
+    from paper_2409_10399_amd.binding import lib
+    from paper_2409_10399_amd.surrogate import _p, _stream
+    B, Hs, Ws, c0, c1, co, up = case
+    H, W = (2 * Hs, 2 * Ws) if up else (Hs, Ws)
+    rng = np.random.default_rng(sum(case))
+    h = rng.normal(size=(B, Hs, Ws, c0)).astype(np.float32)
+    skip = rng.normal(size=(B, H, W, c1)).astype(np.float32)
+    ci = c0 + c1
+    w = (rng.normal(size=(9, ci, co)) / np.sqrt(9 * ci)).astype(np.float32)
+    b = rng.normal(size=co).astype(np.float32)
+    L, st = lib(), _stream()
+    dw_ = dev(w)
+    wf = torch.empty(w.size, dtype=torch.int16, device="cuda")
+    wd = torch.empty(w.size, dtype=torch.int16, device="cuda")
+    assert L.eelbm_cno_pack_weights(_p(dw_), ci, co, _p(wf), _p(wd), st) == 0
+    dh, ds, db_ = dev(h), dev(skip), dev(b)
+    out = torch.empty((B, H, W, co), dtype=torch.float32, device="cuda")
+    assert L.eelbm_cno_conv_fwd_cat(_p(dh), c0, up, _p(ds), c1, B, H, W, _p(wf), _p(db_), co, _p(out), 1, 0.1, st) == 0
+    src = cno.up2(h.astype(np.float64)) if up else h.astype(np.float64)
+    x = np.concatenate([src, skip.astype(np.float64)], axis=3)
+    ref = cno.leaky(cno.conv3x3(bf16(x), bf16(w), b.astype(np.float64)), 0.1)
+    assert rel(host(out), ref) < 2e-6
+    # an odd image cannot be the 2x upsampling of another
+    if up:
+        assert L.eelbm_cno_conv_fwd_cat(_p(dh), c0, 1, _p(ds), c1, B, H - 1, W, _p(wf), _p(db_), co, _p(out), 1, 0.1,
+                                        st) != 0
+
+
+@pytest.mark.parametrize("mt", [1, 2, 4])
+@pytest.mark.parametrize("chans", [(48, 32), (16, 16)])
+def test_every_conv_tile_matches_reference(mt, chans):
+    """Each tile the forward convolution can take (MT x 16 pixels per
+    wavefront, NT x 16 output channels per workgroup), forced, on a ragged
+    image (72 = 64 + 8 columns, 66 = 16 x 4 + 2 rows) with 3 input chunks of
+    32 channels (the last one half full: the next chunk's loads overlap the
+    products) or one (the weights stay in LDS), and more tiles than the chip
+    holds workgroups (each workgroup loops over several); the automatic
+    choice restored after."""
+    import torch
+    from paper_2409_10399_amd.binding import lib
+    from paper_2409_10399_amd.surrogate import _p, _stream
+    B, H, W, co = 3, 66, 72, 192
+    c0, c1 = chans
+    rng = np.random.default_rng(mt + c0)
+    h = rng.normal(size=(B, H // 2, W // 2, c0)).astype(np.float32)
+    skip = rng.normal(size=(B, H, W, c1)).astype(np.float32)
+    ci = c0 + c1
+    w = (rng.normal(size=(9, ci, co)) / np.sqrt(9 * ci)).astype(np.float32)
+    b = rng.normal(size=co).astype(np.float32)
+    L, st = lib(), _stream()
+    dw_ = dev(w)
+    wf = torch.empty(w.size, dtype=torch.int16, device="cuda")
+    wd = torch.empty(w.size, dtype=torch.int16, device="cuda")
+    assert L.eelbm_cno_pack_weights(_p(dw_), ci, co, _p(wf), _p(wd), st) == 0
+    dh, ds, db_ = dev(h), dev(skip), dev(b)
+    x = np.concatenate([cno.up2(h.astype(np.float64)), skip.astype(np.float64)], axis=3)
+    ref = cno.leaky(cno.conv3x3(bf16(x), bf16(w), b.astype(np.float64)), 0.1)
+    out = torch.empty((B, H, W, co), dtype=torch.float32, device="cuda")
+    try:
+        for nt in (1, 2, 3, 4):
+            assert L.eelbm_cno_conv_set_tile(mt, nt) == 0
+            out.fill_(float("nan"))
+            assert L.eelbm_cno_conv_fwd_cat(_p(dh), c0, 1, _p(ds), c1, B, H, W, _p(wf), _p(db_), co, _p(out), 1, 0.1,
+                                            st) == 0, (mt, nt)
+            assert rel(host(out), ref) < 2e-6, (mt, nt)
+        # 48 output channels: 3 N-tiles, which 2 and 4 do not divide
+        assert L.eelbm_cno_conv_set_tile(mt, 2) == 0
+        assert L.eelbm_cno_conv_fwd_cat(_p(dh), c0, 1, _p(ds), c1, B, H, W, _p(wf), _p(db_), 48, _p(out), 1, 0.1,
+                                        st) != 0
+    finally:
+        assert L.eelbm_cno_conv_set_tile(0, 0) == 0
+    assert L.eelbm_cno_conv_set_tile(3, 1) != 0 and L.eelbm_cno_conv_set_tile(1, 5) != 0
+
+
+def test_weight_gradient_is_deterministic():
+    """The weight and bias gradients are sums of per-chunk partials added in a
+    fixed order: two calls give the same bits."""
+    import torch
+    from paper_2409_10399_amd.binding import lib
+    from paper_2409_10399_amd.surrogate import _p, _stream
+    B, H, W, ci, co = 4, 64, 64, 48, 96
+    rng = np.random.default_rng(11)
+    x, g = dev(rng.normal(size=(B, H, W, ci))), dev(rng.normal(size=(B, H, W, co)))
+    L, st = lib(), _stream()
+    res = []
+    for _ in range(2):
+        gw = torch.zeros((9, ci, co), dtype=torch.float32, device="cuda")
+        gb = torch.zeros(co, dtype=torch.float32, device="cuda")
+        assert L.eelbm_cno_conv_bwd_weight(_p(x), _p(g), B, H, W, ci, co, _p(gw), _p(gb), st) == 0
+        res.append((host(gw), host(gb)))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
 def test_elementwise_kernels_match_reference():
     import torch
     from paper_2409_10399_amd.binding import lib
