@@ -318,9 +318,9 @@ int eelbm_cno_conv_fwd_cat(const float* src0, int32_t C0, int32_t up0, const flo
                            int32_t act, float slope, void* stream);
 /* Tile of the forward and input-gradient convolutions, process-wide: mt
  * M-tiles of 16 pixels per wavefront (1, 2 or 4) x nt N-tiles of 16 output
- * channels per workgroup (1..4); (0, 0) restores the automatic choice (the
- * most operand reuse that still gives about four workgroups per compute
- * unit).  For tests and tuning.  A set tile applies to every later call; a
+ * channels per workgroup (1..4); (0, 0) restores the automatic choice (two
+ * M-tiles once W >= 64, else one; two N-tiles if they divide Cout / 16, else
+ * three, else one).  For tests and tuning.  A set tile applies to every later call; a
  * call whose Cout / 16 nt does not divide then returns EELBM_E_PARAM.
  * EELBM_E_PARAM for other values. */
 int eelbm_cno_conv_set_tile(int32_t mt, int32_t nt);
@@ -338,6 +338,19 @@ int eelbm_cno_conv_bwd_data(const float* dout, int32_t B, int32_t H, int32_t W, 
  * Cout <= 256; B * H * W below 2^31 - 4096 pixels (EELBM_E_PARAM otherwise). */
 int eelbm_cno_conv_bwd_weight(const float* in, const float* dout, int32_t B, int32_t H, int32_t W, int32_t Cin,
                               int32_t Cout, float* dw, float* dbias, void* stream);
+/* Gas-volume defect of a surrogate jump f0 -> f1 of N channels, the test
+ * that decides whether a predicted jump is kept or redone on the LBM.
+ * f0, f1: (N, 6, ny, nx) FP32 field planes per channel (alpha_g, u_g,x,
+ * u_g,y, u_l,x, u_l,y, dp_k), rows 0 = inlet .. ny - 1 = outlet; chi: N
+ * FP32 diffusivities c_s^2 (1/omega_alpha - 1/2) of the volume-fraction
+ * schemes (Sec. 2.2); defect: N FP64
+ * results.  Net inflow per step = flux through the inlet row - flux through
+ * the outlet row, each sum over x of alpha_g u_g,y - chi d(alpha_g)/dy (one-
+ * sided difference between the end row and its neighbour); defect =
+ * |V(f1) - V(f0) - jump (in(f0) + in(f1)) / 2| / |V(f0)|, V = sum of alpha_g.
+ * FP64 sums in a fixed order.  ny >= 3; EELBM_E_PARAM otherwise. */
+int eelbm_cno_volume_defect(const float* f0, const float* f1, int32_t N, int32_t ny, int32_t nx, int32_t jump,
+                            const float* chi, double* defect, void* stream);
 /* dx = dy where y > 0, slope * dy elsewhere (y: the leaky-ReLU output). */
 int eelbm_cno_act_bwd(const float* y, const float* dy, int64_t n, float slope, float* dx, void* stream);
 /* 2x2 average pooling (H, W even): forward (B, H, W, C) -> (B, H/2, W/2, C);

@@ -171,3 +171,38 @@ class UNet:
                 grads[i] = (dw, db)
                 t -= 1
         return grads, dh
+
+
+def volume_defect(f0, f1, jump, chi):
+    """Gas-volume defect of a jump f0 -> f1 of a channel (the surrogate's
+    acceptance test), per lattice.  f: (N, 6, ny, nx) field planes (alpha_g,
+    u_g,x, u_g,y, u_l,x, u_l,y, dp_k), rows y = 0 (inlet) .. ny - 1 (outlet);
+    chi: (N,) diffusivity of the volume-fraction scheme.  The gas entering per
+    step is the flux through the inlet row minus that through the outlet row,
+    each advective alpha_g u_g,y plus diffusive -chi d(alpha_g)/dy (one-sided
+    differences between the end row and its neighbour), summed over x; the
+    budget of the jump is jump x the mean of that net inflow at its two ends
+    (trapezoid in time).  Defect = |V(f1) - V(f0) - budget| / |V(f0)|, V the
+    sum of alpha_g over the lattice.  Plain loops over rows and columns in
+    FP64."""
+    f0 = np.asarray(f0, dtype=np.float64)
+    f1 = np.asarray(f1, dtype=np.float64)
+    N, _, ny, nx = f0.shape
+    out = np.zeros(N)
+    for n in range(N):
+        c = float(chi[n])
+
+        def net_inflow(f):
+            a, v = f[n, 0], f[n, 2]
+            s = 0.0
+            for x in range(nx):
+                fin = a[0, x] * v[0, x] - c * (a[1, x] - a[0, x])
+                fout = a[ny - 1, x] * v[ny - 1, x] - c * (a[ny - 1, x] - a[ny - 2, x])
+                s += fin - fout
+            return s
+
+        v0 = f0[n, 0].sum()
+        v1 = f1[n, 0].sum()
+        budget = 0.5 * jump * (net_inflow(f0) + net_inflow(f1))
+        out[n] = abs(v1 - v0 - budget) / abs(v0)
+    return out

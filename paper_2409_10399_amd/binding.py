@@ -78,6 +78,8 @@ SYMBOLS = {
     "eelbm_cno_conv_fwd_cat": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_int32,
                                        c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.c_float, c_void_p]),
     "eelbm_cno_conv_set_tile": (c_int, [c_int32, c_int32]),
+    "eelbm_cno_volume_defect": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                        c_void_p]),
     "eelbm_cno_conv_fwd": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int32,
                                    c_void_p, c_int32, ctypes.c_float, c_void_p]),
     "eelbm_cno_conv_bwd_data": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,

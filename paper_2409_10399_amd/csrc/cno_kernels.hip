@@ -514,6 +514,52 @@ __global__ void k_fill(float* __restrict__ p, long long n, float v) {
         p[i] = v;
 }
 
+// Gas-volume defect of a jump f0 -> f1 per lattice (the surrogate's
+// acceptance test): f (N, 6, ny, nx) field planes, plane 0 alpha_g, plane 2
+// u_g,y; rows 0 (inlet) .. ny - 1 (outlet).  Net inflow per step = inlet-row
+// flux - outlet-row flux, each sum_x alpha u_y - chi d(alpha)/dy (one-sided
+// between the end row and its neighbour); defect = |V1 - V0 - jump (in0 +
+// in1) / 2| / |V0|, V = sum of alpha_g.  One workgroup per lattice, FP64
+// sums reduced in a fixed tree (the result does not depend on the launch).
+__global__ void __launch_bounds__(256) k_volume_defect(const float* __restrict__ f0, const float* __restrict__ f1,
+                                                       int ny, int nx, double jump, const float* __restrict__ chi,
+                                                       double* __restrict__ defect) {
+    __shared__ double red[3][256];
+    const int n = blockIdx.x;
+    const long long plane = (long long)ny * nx;
+    const float* a0 = f0 + (long long)n * 6 * plane;
+    const float* a1 = f1 + (long long)n * 6 * plane;
+    const float* v0 = a0 + 2 * plane;
+    const float* v1 = a1 + 2 * plane;
+    const double c = chi[n];
+    double s0 = 0.0, s1 = 0.0, net = 0.0;
+    for (long long i = threadIdx.x; i < plane; i += 256) {
+        s0 += a0[i];
+        s1 += a1[i];
+    }
+    const long long top = (long long)(ny - 1) * nx, below = (long long)(ny - 2) * nx;
+    for (int x = threadIdx.x; x < nx; x += 256) {
+        double in0 = (double)a0[x] * v0[x] - c * ((double)a0[nx + x] - a0[x]);
+        double out0 = (double)a0[top + x] * v0[top + x] - c * ((double)a0[top + x] - a0[below + x]);
+        double in1 = (double)a1[x] * v1[x] - c * ((double)a1[nx + x] - a1[x]);
+        double out1 = (double)a1[top + x] * v1[top + x] - c * ((double)a1[top + x] - a1[below + x]);
+        net += (in0 - out0) + (in1 - out1);
+    }
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    red[2][threadIdx.x] = net;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double budget = 0.5 * jump * red[2][0];
+        defect[n] = fabs(red[1][0] - red[0][0] - budget) / fabs(red[0][0]);
+    }
+}
+
 // ------------------------------------------------------------- launchers
 inline unsigned grid_for(long long n) {
     long long g = (n + 255) / 256;
@@ -574,31 +620,17 @@ void conv2_m(int nt, const float* src0, int C0, int up0, const float* src1, int 
         default: conv2_mn<MT, 4>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
     }
 }
-// The tile with the most operand reuse (largest MT x NT) among those that
-// still give at least kMinGroups workgroups (four per compute unit), else the
-// one with the most workgroups: the small images of the inner levels need
-// many small tiles to keep the chip busy through their long K loops.
-constexpr long long kMinGroups = 1024;
+// Automatic tile, from a sweep of every tile over the layers of two U-Nets
+// (widths 32/48/96/192 and 16/32/64/128, batch 8 x 256^2) on the MI355X:
+// two M-tiles per wavefront once a row holds them (one below 64 pixels) and
+// two N-tiles, else three, else one.  Four M-tiles were never faster: their
+// larger LDS window and registers leave too few workgroups per compute unit
+// to cover the load latency.
 std::atomic<int> g_tile_mt{0}, g_tile_nt{0};  // eelbm_cno_conv_set_tile; 0: automatic
-void conv2_tile(int B, int H, int W, int Cout, int* mt, int* nt) {
-    static const int order[12][2] = {{4, 4}, {4, 3}, {4, 2}, {2, 4}, {2, 3}, {4, 1},
-                                     {2, 2}, {1, 4}, {1, 3}, {2, 1}, {1, 2}, {1, 1}};
-    long long best = -1;
-    for (const auto& c : order) {
-        const int m = c[0], n = c[1];
-        if ((Cout / 16) % n != 0 || (m > 1 && 16 * m > W)) continue;
-        const long long g = (long long)B * ((H + kRows - 1) / kRows) * ((W + 16 * m - 1) / (16 * m)) * (Cout / (16 * n));
-        if (g >= kMinGroups) {
-            *mt = m;
-            *nt = n;
-            return;
-        }
-        if (g > best) {
-            best = g;
-            *mt = m;
-            *nt = n;
-        }
-    }
+void conv2_tile(int W, int Cout, int* mt, int* nt) {
+    const int n = Cout / 16;
+    *mt = W >= 64 ? 2 : 1;
+    *nt = n % 2 == 0 ? 2 : n % 3 == 0 ? 3 : 1;
 }
 
 // Partial-sum workspace of the weight and bias gradients, held by the library
@@ -650,7 +682,7 @@ int eelbm_cno_conv_fwd_cat(const float* src0, int32_t C0, int32_t up0, const flo
     const unsigned short* w = reinterpret_cast<const unsigned short*>(wf);
     int mt = g_tile_mt.load(), nt = g_tile_nt.load();
     if (mt == 0)
-        conv2_tile(B, H, W, Cout, &mt, &nt);
+        conv2_tile(W, Cout, &mt, &nt);
     else if ((Cout / 16) % nt != 0)
         return EELBM_E_PARAM;
     if (mt == 4)
@@ -717,6 +749,14 @@ int eelbm_cno_conv_bwd_weight(const float* in, const float* dout, int32_t B, int
         e = hipGetLastError();
     }
     return last_rc(e);
+}
+
+int eelbm_cno_volume_defect(const float* f0, const float* f1, int32_t N, int32_t ny, int32_t nx, int32_t jump,
+                            const float* chi, double* defect, void* stream) {
+    if (!f0 || !f1 || !chi || !defect || N < 1 || ny < 3 || nx < 1 || jump < 0) return EELBM_E_PARAM;
+    hipLaunchKernelGGL(k_volume_defect, dim3(N), dim3(256), 0, static_cast<hipStream_t>(stream), f0, f1, ny, nx,
+                       (double)jump, chi, defect);
+    return last_rc(hipGetLastError());
 }
 
 int eelbm_cno_act_bwd(const float* y, const float* dy, int64_t n, float slope, float* dx, void* stream) {

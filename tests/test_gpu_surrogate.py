@@ -149,6 +149,29 @@ def test_every_conv_tile_matches_reference(mt, chans):
     assert L.eelbm_cno_conv_set_tile(3, 1) != 0 and L.eelbm_cno_conv_set_tile(1, 5) != 0
 
 
+@pytest.mark.parametrize("shape", [(3, 40, 24), (1, 3, 1), (2, 256, 300)])
+def test_volume_defect_matches_reference(shape):
+    """eelbm_cno_volume_defect against the FP64 reference on random channel
+    fields (a 300-wide case: more columns than threads; ny = 3: the rows the
+    flux estimate reads overlap)."""
+    import torch
+    from paper_2409_10399_amd.binding import lib
+    from paper_2409_10399_amd.surrogate import _p, _stream
+    N, ny, nx = shape
+    rng = np.random.default_rng(ny)
+    f0 = np.zeros((N, 6, ny, nx), dtype=np.float32)
+    f0[:, 0] = rng.uniform(0.01, 0.2, size=(N, ny, nx))
+    f0[:, 1:5] = rng.normal(0, 0.01, size=(N, 4, ny, nx))
+    f1 = f0 + rng.normal(0, 1e-4, size=f0.shape).astype(np.float32)
+    chi = rng.uniform(0.01, 0.3, size=N).astype(np.float32)
+    out = torch.empty(N, dtype=torch.float64, device="cuda")
+    L = lib()
+    assert L.eelbm_cno_volume_defect(_p(dev(f0)), _p(dev(f1)), N, ny, nx, 100, _p(dev(chi)), _p(out), _stream()) == 0
+    ref = cno.volume_defect(f0, f1, 100, chi.astype(np.float64))
+    np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=1e-9, atol=1e-13)
+    assert L.eelbm_cno_volume_defect(_p(dev(f0)), _p(dev(f1)), N, 2, nx, 100, _p(dev(chi)), _p(out), _stream()) != 0
+
+
 def test_weight_gradient_is_deterministic():
     """The weight and bias gradients are sums of per-chunk partials added in a
     fixed order: two calls give the same bits."""

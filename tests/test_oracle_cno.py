@@ -92,3 +92,54 @@ def test_adam_first_step_moves_by_lr():
     w = np.array([1.0, -2.0]); g = np.array([0.5, -3.0])
     w1, m, v = cno.adam(w, g, np.zeros(2), np.zeros(2), 1, lr=0.01)
     assert np.allclose(w1, w - 0.01 * np.sign(g), atol=1e-7)
+
+
+def _channel_fields(rng, N, ny, nx):
+    f = np.zeros((N, 6, ny, nx))
+    f[:, 0] = rng.uniform(0.01, 0.2, size=(N, ny, nx))
+    f[:, 1:5] = rng.normal(0.0, 0.01, size=(N, 4, ny, nx))
+    return f
+
+
+def test_volume_defect_pins():
+    """volume_defect against what the definition fixes: (1) a uniform, still
+    field has no flux and no change, defect 0; (2) gas added uniformly with
+    no flux: defect = added volume / initial volume exactly; (3) a discrete
+    advection-diffusion update of alpha_g along y (upwind flux alpha u_y plus
+    -chi (a[y+1] - a[y]) between rows, zero flux at the side columns) conserves
+    the total up to the fluxes through the end faces, and with u_y, chi
+    constant in time and the end rows unchanged the defect measures only the
+    fluxes through its end rows: a step built from those fluxes has defect 0
+    as a jump of 1 and one step's net inflow as a jump of 2."""
+    rng = np.random.default_rng(3)
+    # (1)
+    f = np.zeros((2, 6, 8, 5))
+    f[:, 0] = 0.1
+    assert np.all(cno.volume_defect(f, f.copy(), 100, [0.1, 0.2]) == 0.0)
+    # (2)
+    g = f.copy()
+    g[:, 0] += 1e-3
+    np.testing.assert_allclose(cno.volume_defect(f, g, 100, [0.1, 0.2]), 1e-3 / 0.1, rtol=1e-12)
+    # (3) one explicit step with face fluxes F[y] between row y-1 and y; the
+    # inflow through the inlet face and the outflow through the outlet face
+    # are set to the same one-sided expressions the defect uses, so the
+    # defect of the step is 0 to rounding when f0 and f1 share end rows
+    ny, nx, chi = 12, 7, 0.05
+    f0 = _channel_fields(rng, 1, ny, nx)
+    a, v = f0[0, 0], f0[0, 2]
+    fin = a[0] * v[0] - chi * (a[1] - a[0])
+    fout = a[-1] * v[-1] - chi * (a[-1] - a[-2])
+    f1 = f0.copy()
+    # move gas between interior rows 2..ny-3 only (no net change), then add
+    # the end fluxes to rows 2 and ny - 3 (not read by the flux estimate)
+    for y in range(2, ny - 3):
+        flux = a[y] * v[y] - chi * (a[y + 1] - a[y])
+        f1[0, 0, y] -= flux
+        f1[0, 0, y + 1] += flux
+    f1[0, 0, 2] += fin
+    f1[0, 0, ny - 3] -= fout
+    d = cno.volume_defect(f0, f1, 1, [chi])
+    assert d[0] < 1e-14
+    # the same step taken as a jump of 2 is off by exactly one step's net inflow
+    d2 = cno.volume_defect(f0, f1, 2, [chi])
+    np.testing.assert_allclose(d2[0], abs((fin - fout).sum()) / a.sum(), rtol=1e-9)

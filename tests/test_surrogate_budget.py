@@ -3,12 +3,20 @@ the defect of a jump that moves exactly the inflow budget into the domain is
 zero, the sign of the flux terms (gas entering through row 0 and leaving
 through the last row) is fixed by hand-built fields, and `conserve` brings a
 perturbed prediction onto the budget without touching the rows the flux
-estimate reads or the other field planes."""
+estimate reads or the other field planes.  The defect here is the FP64
+reference (oracle/cno.py, volume_defect); the GPU kernel that the rollout
+calls is compared with it in tests/test_gpu_surrogate.py."""
 import numpy as np
 import pytest
 import torch
 
-from paper_2409_10399_amd.surrogate_study import conserve, defect
+from oracle.cno import volume_defect
+from paper_2409_10399_amd.surrogate_study import conserve
+
+
+def defect(f0, f1, jump, chi):
+    return volume_defect(f0.numpy(), f1.numpy(), jump, chi.numpy())
+
 
 pytestmark = pytest.mark.filterwarnings("ignore")
 
