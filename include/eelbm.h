@@ -243,7 +243,11 @@ int eelbm_map_physical(double g, double kappa_I, double g_hat, double kappa_hat,
 typedef struct eelbm_batch eelbm_batch;
 
 /* Device bytes of the batch's work area (member table, work list, clock) for
- * the tile shape tile_x * tile_y (tile_x a multiple of 64, at most 256 nodes). */
+ * the tile shape tile_x * tile_y (tile_x a multiple of 64, at most 256 nodes).
+ * tile_x = tile_y = 0 takes the tile eelbm_autotune picks for the largest
+ * member (timed on that member alone, its state restored bit for bit; the
+ * choice is cached per lattice, storage, boundary kind and size class, so
+ * eelbm_batch_bytes and eelbm_batch_create given 0, 0 agree). */
 int eelbm_batch_bytes(eelbm_handle* const* members, int32_t n, int32_t tile_x, int32_t tile_y, size_t* bytes);
 
 /* Bind caller-owned device memory (eelbm_batch_bytes, 256-byte aligned) and

@@ -59,22 +59,30 @@ def time_case(cfg, fields, storage, steps, warmup):
     return e0.elapsed_time(e1) * 1e3 / steps, ok
 
 
-def batch_cases(count, steps, seed=0, tile=(64, 4), graph_steps=100):
+def batch_cases(count, steps, seed=0, tile=(64, 4), graph_steps=100, modes=("graph", "batched", "separate"),
+                grid=0):
     """The channel sweep (count members, FP32) advanced three ways from its
     initial state: one batched launch per step replayed from HIP graphs of
     graph_steps steps, one batched launch per step, and every member launched
-    on its own (steps / 20 steps)."""
+    on its own (steps / 20 steps).  tile None: the batch's autotuned tile.
+    grid > 0: count channels of grid x grid nodes (the surrogate study's
+    distribution) instead of the sweep's uneven sizes."""
     import torch
     import workloads
     from paper_2409_10399_amd import Batch, Lattice
     t0 = time.time()
-    ws = workloads.channel_sweep(count=count, seed=seed)
+    if grid:
+        from paper_2409_10399_amd.surrogate_study import instances
+        ws = [(cfg, f) for cfg, f, _ in instances(count, seed=seed + 1, n=grid)]
+    else:
+        ws = workloads.channel_sweep(count=count, seed=seed)
     nodes = sum(c["nx"] * c["ny"] for c, _ in ws)
     lats = []
     for cfg, f in ws:
         lat = Lattice(cfg, storage="fp32")
         lat.init_fields(f)
-        lat.set_launch(*tile)
+        if tile is not None:
+            lat.set_launch(*tile)
         lats.append(lat)
     torch.cuda.synchronize()
     print(f"# sweep: {count} channels, {nodes} nodes, set up in {time.time() - t0:.1f} s", flush=True)
@@ -90,7 +98,7 @@ def batch_cases(count, steps, seed=0, tile=(64, 4), graph_steps=100):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) * 1e3 / n
 
-    for mode in ("graph", "batched", "separate"):
+    for mode in modes:
         for lat, (cfg, f) in zip(lats, ws):  # every mode starts from the initial state
             lat.init_fields(f)
         if mode == "separate":
@@ -103,7 +111,9 @@ def batch_cases(count, steps, seed=0, tile=(64, 4), graph_steps=100):
             del b
         ok = all(lat.diag()["nonfinite"] == 0 for lat in lats)
         bpn = bytes_per_node(2, 9, "fp32", True)
-        r = {"case": f"sweep{count}", "mode": mode, "nodes": nodes, "us_per_step": round(us, 2),
+        r = {"case": f"sweep{count}" + (f"x{grid}^2" if grid else ""), "mode": mode,
+             "tile": "x".join(map(str, lats[0].get_launch()[:2])) + (" (auto)" if tile is None else ""),
+             "nodes": nodes, "us_per_step": round(us, 2),
              "MLUPS": round(nodes / us, 1), "GB_s": round(bpn * nodes / us / 1e3, 1),
              "frac_hbm_peak": round(bpn * nodes / us / 1e3 / HBM_PEAK_GBS, 4), "finite": bool(ok)}
         rows.append(r)
@@ -119,9 +129,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--sweep", type=int, default=0, help="members of the batched channel sweep (0: skip)")
     ap.add_argument("--sweep-steps", type=int, default=500)
+    ap.add_argument("--sweep-tiles", default="64x4", help="tiles of the sweep batch, e.g. 64x4,128x2,auto")
+    ap.add_argument("--sweep-modes", default="graph,batched,separate")
+    ap.add_argument("--sweep-grid", type=int, default=0, help="square channels of this size (0: the sweep's sizes)")
     a = ap.parse_args()
     if a.sweep:
-        batch_cases(a.sweep, a.sweep_steps)
+        for t in a.sweep_tiles.split(","):
+            tile = None if t == "auto" else tuple(int(v) for v in t.split("x"))
+            batch_cases(a.sweep, a.sweep_steps, tile=tile, modes=a.sweep_modes.split(","), grid=a.sweep_grid)
         return
     rows = []
     for case in a.cases.split(","):

@@ -307,11 +307,13 @@ class Lattice:
 
 class Batch:
     """Lattices advanced together: one launch per step over all their tiles,
-    optionally captured in HIP graphs of `graph_steps` steps."""
+    optionally captured in HIP graphs of `graph_steps` steps.  tile=None: the
+    autotuned tile of the largest member."""
 
-    def __init__(self, members, tile=(64, 4), graph_steps=0, stream=None):
+    def __init__(self, members, tile=None, graph_steps=0, stream=None):
         import torch
         L = lib()
+        tile = (0, 0) if tile is None else tile
         self.members = list(members)
         arr = (c_void_p * len(self.members))(*[m.h for m in self.members])
         self._arr = arr

@@ -849,13 +849,28 @@ int batch_step_launches(eelbm_batch* b, int64_t nsteps, hipStream_t s) {
     return EELBM_OK;
 }
 
+// tile_x = tile_y = 0: the autotuned tile of the largest member (by node count)
+constexpr int kBatchTuneSteps = 20;
+int resolve_batch_tile(eelbm_handle* const* members, int32_t n, int32_t* tile_x, int32_t* tile_y) {
+    if (*tile_x != 0 || *tile_y != 0) return EELBM_OK;
+    if (!members || n < 1) return fail(EELBM_E_PARAM, "a batch needs at least one lattice");
+    eelbm_handle* big = nullptr;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!members[i]) return fail(EELBM_E_PARAM, "batch member is NULL");
+        if (!big || members[i]->g.n > big->g.n) big = members[i];
+    }
+    return eelbm_autotune(big, kBatchTuneSteps, 0, tile_x, tile_y, nullptr);
+}
+
 }  // namespace
 
 extern "C" {
 
 int eelbm_batch_bytes(eelbm_handle* const* members, int32_t n, int32_t tile_x, int32_t tile_y, size_t* bytes) {
     if (!bytes) return fail(EELBM_E_PARAM, "bytes is NULL");
-    int rc = check_members(members, n, tile_x, tile_y);
+    int rc = resolve_batch_tile(members, n, &tile_x, &tile_y);
+    if (rc) return rc;
+    rc = check_members(members, n, tile_x, tile_y);
     if (rc) return rc;
     *bytes = batch_sizes(members, n, tile_x, tile_y).total;
     return EELBM_OK;
@@ -865,7 +880,9 @@ int eelbm_batch_create(eelbm_handle* const* members, int32_t n, int32_t tile_x, 
                        size_t bytes, void* hip_stream, eelbm_batch** out) {
     if (!out) return fail(EELBM_E_PARAM, "out is NULL");
     *out = nullptr;
-    int rc = check_members(members, n, tile_x, tile_y);
+    int rc = resolve_batch_tile(members, n, &tile_x, &tile_y);
+    if (rc) return rc;
+    rc = check_members(members, n, tile_x, tile_y);
     if (rc) return rc;
     const BatchSizes z = batch_sizes(members, n, tile_x, tile_y);
     if (!device_mem) return fail(EELBM_E_PARAM, "device_mem is NULL");

@@ -189,3 +189,26 @@ def test_autotune_keeps_state_and_results():
     # cached for the size class: a second lattice of the class gets it without timing
     c = run_gpu(cfg, f, 0, "fp32")
     assert c.autotune(steps=5) == shape
+
+
+def test_batch_with_autotuned_tile():
+    # tile None: the batch takes the tile the autotuner picks for its largest
+    # member (timed on that member, its state restored); every member then
+    # runs with it and the results equal the members advanced alone with it
+    from paper_2409_10399_amd import Batch
+    ws = members()
+    alone = _lattices(ws, "fp32")
+    batched = _lattices(ws, "fp32")
+    batch = Batch(batched, graph_steps=8)
+    tiles = {lat.get_launch()[:2] for lat in batched}
+    assert len(tiles) == 1
+    tx, ty = tiles.pop()
+    assert tx % 64 == 0 and tx * ty <= 256
+    for n in (8, 5):
+        batch.advance(n)
+        for lat in alone:
+            lat.set_launch(tx, ty)
+            lat.advance(n)
+        for a, b in zip(alone, batched):
+            for k in FIELDS:
+                assert np.array_equal(a.read(k), b.read(k)), (n, k)
