@@ -183,6 +183,16 @@ int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g,
 int eelbm_reinit_fields(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u_g, const double* u_l,
                         const double* dp_k, int on_device);
 
+/* eelbm_reinit_fields from device fields (all four given), carried out only
+ * if the device flag *gate (an int32 in device memory) is nonzero when the
+ * rebuild runs on the device; with *gate == 0 the state is left as it was.
+ * The host side (time, copy parity) is set to t either way, so a caller
+ * gates only lattices already at t or lattices whose state it will not use
+ * before another rebuild.  For rollouts that decide on the device which
+ * lattices to rebuild, without waiting for the device. */
+int eelbm_reinit_fields_gated(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u_g,
+                              const double* u_l, const double* dp_k, const int32_t* gate);
+
 /* Advance nsteps time steps (asynchronous on the bound stream).  The last
  * step also writes the output fields and the diagnostic partial sums. */
 int eelbm_advance(eelbm_handle* h, int64_t nsteps);
@@ -264,6 +274,30 @@ int eelbm_batch_create(eelbm_handle* const* members, int32_t n, int32_t tile_x, 
  * launched directly).  Every step reads its time from a device clock, so a
  * replay is valid at any time. */
 int eelbm_batch_set_graph(eelbm_batch* b, int32_t steps_per_graph);
+
+/* Device flags, one int32 per member in member order (device memory the
+ * caller keeps alive), read on the device at the start of every
+ * eelbm_batch_advance: a member whose flag is 0 is not advanced by it.  Its
+ * populations are left untouched while its time moves with the batch, so
+ * its state is not valid until it is rebuilt (eelbm_reinit_fields,
+ * eelbm_reinit_fields_gated): reads and diagnostics of it return stale
+ * values.  The tiles of the active members are gathered into a work list of
+ * their own on the device (so they spread over the whole GPU whichever
+ * members are left out); flags may change on the device between advances,
+ * also under graph replay.  NULL: every member advances.  For advancing only
+ * the members a device-side test selected, without waiting for the device. */
+int eelbm_batch_set_active(eelbm_batch* b, const int32_t* active);
+
+/* eelbm_reinit_fields_gated for every member at time t, member i gated by
+ * gate[i] (device int32 flags).  fields: device FP64, the members one after
+ * the other, each [2 + 2D][n]: alpha_g, u_g (D planes), u_l (D planes), dp_k.
+ * Asynchronous (no wait for the device). */
+int eelbm_batch_rebuild_gated(eelbm_batch* b, int64_t t, const double* fields, const int32_t* gate);
+
+/* The output fields of every member (as eelbm_read after the last advance),
+ * FP32, into device memory laid out like the fields of
+ * eelbm_batch_rebuild_gated.  Asynchronous. */
+int eelbm_batch_read_fields(eelbm_batch* b, float* out);
 
 /* Advance every member by nsteps (asynchronous).  The last step of the
  * advance (and of every replayed graph) writes the output fields and
@@ -352,9 +386,25 @@ int eelbm_cno_conv_bwd_weight(const float* in, const float* dout, int32_t B, int
  * the outlet row, each sum over x of alpha_g u_g,y - chi d(alpha_g)/dy (one-
  * sided difference between the end row and its neighbour); defect =
  * |V(f1) - V(f0) - jump (in(f0) + in(f1)) / 2| / |V(f0)|, V = sum of alpha_g.
- * FP64 sums in a fixed order.  ny >= 3; EELBM_E_PARAM otherwise. */
+ * FP64 sums in a fixed order.  ny >= 3 and f0, f1 16-byte aligned;
+ * EELBM_E_PARAM otherwise. */
 int eelbm_cno_volume_defect(const float* f0, const float* f1, int32_t N, int32_t ny, int32_t nx, int32_t jump,
                             const float* chi, double* defect, void* stream);
+/* The re-anchoring decision of a surrogate rollout jump for N lattices, on
+ * the device (one thread block, no host wait): mask[i] = 1 if defect[i]
+ * exceeds defect_max or is not finite, or if force != 0; rebuild[i] =
+ * mask[i] && !valid[i] (the lattice's LBM state is not at the current time
+ * and must be rebuilt from the fields before it is advanced); then valid[i]
+ * = mask[i] and *count += the number of masked lattices.  All arrays are
+ * device memory: defect N doubles, valid, mask, rebuild N int32, count one
+ * int64. */
+int eelbm_cno_reanchor_policy(const double* defect, int32_t N, double defect_max, int32_t force, int32_t* valid,
+                              int32_t* mask, int32_t* rebuild, int64_t* count, void* stream);
+/* out[i] = mask[i / per] ? a[i] : b[i] for i < N * per (device arrays; out
+ * may alias a or b): the fields of the re-anchored lattices taken from the
+ * LBM, the others from the surrogate. */
+int eelbm_cno_select(const int32_t* mask, int32_t N, int64_t per, const float* a, const float* b, float* out,
+                     void* stream);
 /* dx = dy where y > 0, slope * dy elsewhere (y: the leaky-ReLU output). */
 int eelbm_cno_act_bwd(const float* y, const float* dy, int64_t n, float slope, float* dx, void* stream);
 /* 2x2 average pooling (H, W even): forward (B, H, W, C) -> (B, H/2, W/2, C);

@@ -80,6 +80,13 @@ SYMBOLS = {
     "eelbm_cno_conv_set_tile": (c_int, [c_int32, c_int32]),
     "eelbm_cno_volume_defect": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p,
                                         c_void_p]),
+    "eelbm_cno_reanchor_policy": (c_int, [c_void_p, c_int32, ctypes.c_double, c_int32, c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_void_p]),
+    "eelbm_cno_select": (c_int, [c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "eelbm_reinit_fields_gated": (c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "eelbm_batch_set_active": (c_int, [c_void_p, c_void_p]),
+    "eelbm_batch_rebuild_gated": (c_int, [c_void_p, c_int64, c_void_p, c_void_p]),
+    "eelbm_batch_read_fields": (c_int, [c_void_p, c_void_p]),
     "eelbm_cno_conv_fwd": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int32,
                                    c_void_p, c_int32, ctypes.c_float, c_void_p]),
     "eelbm_cno_conv_bwd_data": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p,
@@ -237,10 +244,16 @@ class Lattice:
         _check(lib().eelbm_init_fields(self.h, ptr("alpha_g"), ptr("u_g"), ptr("u_l"), ptr("dp_k"),
                                        ptr("inlet_noise"), 1))
 
-    def reinit_fields_device(self, t, tensors):
-        """Rebuild the state at time t from device (torch float64) fields."""
+    def reinit_fields_device(self, t, tensors, gate=None):
+        """Rebuild the state at time t from device (torch float64) fields;
+        gate: a device int32 tensor element (a one-element view): rebuild
+        only if it is nonzero when the rebuild runs."""
         ptr = lambda k: c_void_p(tensors[k].data_ptr()) if tensors.get(k) is not None else None
-        _check(lib().eelbm_reinit_fields(self.h, int(t), ptr("alpha_g"), ptr("u_g"), ptr("u_l"), ptr("dp_k"), 1))
+        if gate is None:
+            _check(lib().eelbm_reinit_fields(self.h, int(t), ptr("alpha_g"), ptr("u_g"), ptr("u_l"), ptr("dp_k"), 1))
+        else:
+            _check(lib().eelbm_reinit_fields_gated(self.h, int(t), ptr("alpha_g"), ptr("u_g"), ptr("u_l"),
+                                                   ptr("dp_k"), c_void_p(gate.data_ptr())))
 
     def advance(self, nsteps):
         _check(lib().eelbm_advance(self.h, int(nsteps)))
@@ -330,6 +343,24 @@ class Batch:
 
     def set_graph(self, steps):
         _check(lib().eelbm_batch_set_graph(self.b, int(steps)))
+
+    def rebuild_gated(self, t, fields, gate):
+        """Rebuild member i at time t from fields[i] (device float64, the
+        members' [2 + 2D][n] field planes one after the other) where gate[i]
+        (device int32) is nonzero when the rebuild runs."""
+        _check(lib().eelbm_batch_rebuild_gated(self.b, int(t), c_void_p(fields.data_ptr()),
+                                               c_void_p(gate.data_ptr())))
+
+    def read_fields(self, out):
+        """Every member's output fields into out (device float32, the layout
+        of rebuild_gated)."""
+        _check(lib().eelbm_batch_read_fields(self.b, c_void_p(out.data_ptr())))
+
+    def set_active(self, flags):
+        """flags: device int32 tensor, one per member (kept alive by the
+        batch), read at every step; None: every member advances."""
+        self._active = flags
+        _check(lib().eelbm_batch_set_active(self.b, c_void_p(flags.data_ptr()) if flags is not None else None))
 
     def advance(self, nsteps):
         _check(lib().eelbm_batch_advance(self.b, int(nsteps)))

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <atomic>
 #include <cmath>
 #include <mutex>
@@ -519,12 +520,16 @@ __global__ void k_fill(float* __restrict__ p, long long n, float v) {
 // u_g,y; rows 0 (inlet) .. ny - 1 (outlet).  Net inflow per step = inlet-row
 // flux - outlet-row flux, each sum_x alpha u_y - chi d(alpha)/dy (one-sided
 // between the end row and its neighbour); defect = |V1 - V0 - jump (in0 +
-// in1) / 2| / |V0|, V = sum of alpha_g.  One workgroup per lattice, FP64
-// sums reduced in a fixed tree (the result does not depend on the launch).
-__global__ void __launch_bounds__(256) k_volume_defect(const float* __restrict__ f0, const float* __restrict__ f1,
-                                                       int ny, int nx, double jump, const float* __restrict__ chi,
-                                                       double* __restrict__ defect) {
-    __shared__ double red[3][256];
+// in1) / 2| / |V0|, V = sum of alpha_g.  One workgroup of 1024 threads per
+// lattice (16-byte loads when the plane allows, four loads in flight per
+// thread), FP64 sums reduced in a fixed tree: the result does not depend on
+// the launch.
+constexpr int kDefThreads = 1024;
+__global__ void __launch_bounds__(kDefThreads) k_volume_defect(const float* __restrict__ f0,
+                                                               const float* __restrict__ f1, int ny, int nx,
+                                                               double jump, const float* __restrict__ chi,
+                                                               double* __restrict__ defect) {
+    __shared__ double red[3][kDefThreads];
     const int n = blockIdx.x;
     const long long plane = (long long)ny * nx;
     const float* a0 = f0 + (long long)n * 6 * plane;
@@ -533,12 +538,39 @@ __global__ void __launch_bounds__(256) k_volume_defect(const float* __restrict__
     const float* v1 = a1 + 2 * plane;
     const double c = chi[n];
     double s0 = 0.0, s1 = 0.0, net = 0.0;
-    for (long long i = threadIdx.x; i < plane; i += 256) {
+    long long done = 0;
+    if ((plane & 3) == 0) {
+        // f0, f1 16-byte aligned (host check), plane a multiple of 4 values
+        const float4* b0 = reinterpret_cast<const float4*>(a0);
+        const float4* b1 = reinterpret_cast<const float4*>(a1);
+        const long long n4 = plane >> 2;
+        long long i = threadIdx.x;
+        for (; i + 3 * kDefThreads < n4; i += 4 * kDefThreads) {
+            float4 x[4], y[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                x[u] = b0[i + u * kDefThreads];
+                y[u] = b1[i + u * kDefThreads];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                s0 += ((double)x[u].x + x[u].y) + ((double)x[u].z + x[u].w);
+                s1 += ((double)y[u].x + y[u].y) + ((double)y[u].z + y[u].w);
+            }
+        }
+        for (; i < n4; i += kDefThreads) {
+            const float4 x = b0[i], y = b1[i];
+            s0 += ((double)x.x + x.y) + ((double)x.z + x.w);
+            s1 += ((double)y.x + y.y) + ((double)y.z + y.w);
+        }
+        done = plane;
+    }
+    for (long long i = done + threadIdx.x; i < plane; i += kDefThreads) {
         s0 += a0[i];
         s1 += a1[i];
     }
     const long long top = (long long)(ny - 1) * nx, below = (long long)(ny - 2) * nx;
-    for (int x = threadIdx.x; x < nx; x += 256) {
+    for (int x = threadIdx.x; x < nx; x += kDefThreads) {
         double in0 = (double)a0[x] * v0[x] - c * ((double)a0[nx + x] - a0[x]);
         double out0 = (double)a0[top + x] * v0[top + x] - c * ((double)a0[top + x] - a0[below + x]);
         double in1 = (double)a1[x] * v1[x] - c * ((double)a1[nx + x] - a1[x]);
@@ -549,7 +581,7 @@ __global__ void __launch_bounds__(256) k_volume_defect(const float* __restrict__
     red[1][threadIdx.x] = s1;
     red[2][threadIdx.x] = net;
     __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
+    for (int k = kDefThreads / 2; k > 0; k >>= 1) {
         if ((int)threadIdx.x < k)
             for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + k];
         __syncthreads();
@@ -558,6 +590,37 @@ __global__ void __launch_bounds__(256) k_volume_defect(const float* __restrict__
         const double budget = 0.5 * jump * red[2][0];
         defect[n] = fabs(red[1][0] - red[0][0] - budget) / fabs(red[0][0]);
     }
+}
+
+// Re-anchoring decision of a rollout jump, on the device: mask[i] = the jump
+// of lattice i is redone on the LBM (defect above defect_max or not finite,
+// or every lattice when force != 0); rebuild[i] = mask[i] and the lattice's
+// LBM state is not the current one (valid[i] == 0), i.e. it must be rebuilt
+// from the fields first; then valid[i] = mask[i] (the re-anchored lattices
+// hold the LBM state of the next time) and count += the masked lattices.
+__global__ void k_reanchor_policy(const double* __restrict__ defect, int N, double defect_max, int force,
+                                  int* __restrict__ valid, int* __restrict__ mask, int* __restrict__ rebuild,
+                                  long long* __restrict__ count) {
+    __shared__ int nm;
+    if (threadIdx.x == 0) nm = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const double d = defect[i];
+        const int m = (force != 0 || !(d <= defect_max)) ? 1 : 0;  // NaN compares false: masked
+        mask[i] = m;
+        rebuild[i] = m && !valid[i];
+        valid[i] = m;
+        if (m) atomicAdd(&nm, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) count[0] += nm;
+}
+
+// out[i] = mask[i / per] ? a[i] : b[i] over N blocks of per values
+__global__ void k_select(const int* __restrict__ mask, long long n, long long per, const float* __restrict__ a,
+                         const float* __restrict__ b, float* __restrict__ out) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = mask[i / per] ? a[i] : b[i];
 }
 
 // ------------------------------------------------------------- launchers
@@ -754,8 +817,26 @@ int eelbm_cno_conv_bwd_weight(const float* in, const float* dout, int32_t B, int
 int eelbm_cno_volume_defect(const float* f0, const float* f1, int32_t N, int32_t ny, int32_t nx, int32_t jump,
                             const float* chi, double* defect, void* stream) {
     if (!f0 || !f1 || !chi || !defect || N < 1 || ny < 3 || nx < 1 || jump < 0) return EELBM_E_PARAM;
-    hipLaunchKernelGGL(k_volume_defect, dim3(N), dim3(256), 0, static_cast<hipStream_t>(stream), f0, f1, ny, nx,
-                       (double)jump, chi, defect);
+    if ((reinterpret_cast<uintptr_t>(f0) & 15) || (reinterpret_cast<uintptr_t>(f1) & 15)) return EELBM_E_PARAM;
+    hipLaunchKernelGGL(k_volume_defect, dim3(N), dim3(kDefThreads), 0, static_cast<hipStream_t>(stream), f0, f1, ny,
+                       nx, (double)jump, chi, defect);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_reanchor_policy(const double* defect, int32_t N, double defect_max, int32_t force, int32_t* valid,
+                              int32_t* mask, int32_t* rebuild, int64_t* count, void* stream) {
+    if (!defect || !valid || !mask || !rebuild || !count || N < 1) return EELBM_E_PARAM;
+    hipLaunchKernelGGL(k_reanchor_policy, dim3(1), dim3(256), 0, static_cast<hipStream_t>(stream), defect, N,
+                       defect_max, force, valid, mask, rebuild, reinterpret_cast<long long*>(count));
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_select(const int32_t* mask, int32_t N, int64_t per, const float* a, const float* b, float* out,
+                     void* stream) {
+    if (!mask || !a || !b || !out || N < 1 || per < 1) return EELBM_E_PARAM;
+    const long long n = (long long)N * per;
+    hipLaunchKernelGGL(k_select, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), mask, n, per, a,
+                       b, out);
     return last_rc(hipGetLastError());
 }
 

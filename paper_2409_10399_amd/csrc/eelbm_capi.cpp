@@ -337,9 +337,10 @@ void fill_kparams(eelbm_handle* h) {
     k.h16_down[1] = std::ldexp(1.0f, -(20 + e));
 }
 
-int launch(eelbm_handle* h, bool init, int64_t t, bool last) {
+int launch(eelbm_handle* h, bool init, int64_t t, bool last, const int32_t* gate = nullptr) {
     KCtl c{};
     c.t = t;
+    c.gate = gate;
     // lagged S'' and Lambda' (Eqs. (133), (137)) refresh at t mod n_gamma == 0
     // and at the first step of a run or rebuild: fields bring no lagged values
     c.refresh = init || (t % h->p.n_gamma) == 0;
@@ -425,7 +426,8 @@ namespace {
 // initial state (keep = false) or rebuilt state at time t (keep = true:
 // inlet noise, buoyancy reference and lag fields are those of the run)
 int init_impl(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u_g, const double* u_l,
-              const double* dp_k, const double* inlet_noise, int on_device, bool keep) {
+              const double* dp_k, const double* inlet_noise, int on_device, bool keep,
+              const int32_t* gate = nullptr) {
     if (!h) return fail(EELBM_E_PARAM, "handle is NULL");
     if (!alpha_g) return fail(EELBM_E_PARAM, "alpha_g is NULL");
     if (keep && !h->initialized) return fail(EELBM_E_STATE, "eelbm_init_fields not called");
@@ -495,7 +497,7 @@ int init_impl(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u
     h->b_l = (h->rho_ref / p.rho_l - 1.0) * p.g_hat;
     fill_kparams(h);
     if (!keep) ++h->gen;
-    rc = launch(h, true, t, true);
+    rc = launch(h, true, t, true, gate);
     if (rc) return rc;
     if (!on_device) {
         // host inputs were copied from pageable memory; finish before returning
@@ -517,6 +519,13 @@ int eelbm_init_fields(eelbm_handle* h, const double* alpha_g, const double* u_g,
 int eelbm_reinit_fields(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u_g, const double* u_l,
                         const double* dp_k, int on_device) {
     return init_impl(h, t, alpha_g, u_g, u_l, dp_k, nullptr, on_device, true);
+}
+
+int eelbm_reinit_fields_gated(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u_g, const double* u_l,
+                              const double* dp_k, const int32_t* gate) {
+    if (!gate) return fail(EELBM_E_PARAM, "gate is NULL");
+    if (!u_g || !u_l || !dp_k) return fail(EELBM_E_PARAM, "a gated rebuild needs every field");
+    return init_impl(h, t, alpha_g, u_g, u_l, dp_k, nullptr, 1, true, gate);
 }
 
 int eelbm_advance(eelbm_handle* h, int64_t nsteps) {
@@ -792,6 +801,8 @@ struct eelbm_batch {
     int exec_steps;
     long long t_clock;  // time the device clock holds (members may be rebuilt at another time between advances)
     bool nt_store;      // the members' populations together exceed the last-level cache
+    const int32_t* active;  // device flags per member (NULL: all advance)
+    size_t off_moff, off_aoff, off_awork, off_count;
 };
 
 namespace {
@@ -821,8 +832,11 @@ int check_members(eelbm_handle* const* m, int32_t n, int32_t tx, int32_t ty) {
     return EELBM_OK;
 }
 
+// device layout of a batch: member table | work list | clock | member
+// offsets in the work list (n + 1) | active members' offsets (n) | work list
+// of the active members | its length
 struct BatchSizes {
-    size_t lat, work, clock, total;
+    size_t lat, work, clock, moff, aoff, awork, count, total;
     long long nwork;
 };
 BatchSizes batch_sizes(eelbm_handle* const* m, int32_t n, int32_t tx, int32_t ty) {
@@ -831,17 +845,23 @@ BatchSizes batch_sizes(eelbm_handle* const* m, int32_t n, int32_t tx, int32_t ty
     z.lat = 0;
     z.work = align256((size_t)n * sizeof(BatchLattice));
     z.clock = z.work + align256((size_t)z.nwork * sizeof(uint2));
-    z.total = z.clock + 256;
+    z.moff = z.clock + 256;
+    z.aoff = z.moff + align256((size_t)(n + 1) * sizeof(int));
+    z.awork = z.aoff + align256((size_t)n * sizeof(int));
+    z.count = z.awork + align256((size_t)z.nwork * sizeof(uint2));
+    z.total = z.count + 256;
     return z;
 }
 
 int batch_step_launches(eelbm_batch* b, int64_t nsteps, hipStream_t s) {
     const BatchLattice* lat = reinterpret_cast<const BatchLattice*>(b->mem + b->off_lat);
-    const uint2* work = reinterpret_cast<const uint2*>(b->mem + b->off_work);
+    // with active flags: the compacted work list and its length on the device
+    const uint2* work = reinterpret_cast<const uint2*>(b->mem + (b->active ? b->off_awork : b->off_work));
+    const int* count = b->active ? reinterpret_cast<const int*>(b->mem + b->off_count) : nullptr;
     long long* clock = reinterpret_cast<long long*>(b->mem + b->off_clock);
     for (int64_t k = 0; k < nsteps; ++k) {
         hipError_t e = launch_batch_step(b->lattice, b->storage, b->bc_mode, b->nt_store, lat, work, b->nwork, clock, (int)k,
-                                         k == nsteps - 1, b->block, s);
+                                         k == nsteps - 1, count, b->block, s);
         if (e != hipSuccess) return hip_fail(e, "batch step launch");
     }
     hipError_t e = launch_clock_add(clock, nsteps, s);
@@ -922,6 +942,10 @@ int eelbm_batch_create(eelbm_handle* const* members, int32_t n, int32_t tile_x, 
     b->off_lat = z.lat;
     b->off_work = z.work;
     b->off_clock = z.clock;
+    b->off_moff = z.moff;
+    b->off_aoff = z.aoff;
+    b->off_awork = z.awork;
+    b->off_count = z.count;
     b->nwork = z.nwork;
     b->block = dim3(tile_x, tile_y, 1);
     b->graph_steps = 0;
@@ -939,6 +963,11 @@ int eelbm_batch_create(eelbm_handle* const* members, int32_t n, int32_t tile_x, 
                            b->own);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->mem + b->off_clock, &t0, sizeof(t0), hipMemcpyHostToDevice, b->own);
+    std::vector<int> moff((size_t)n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) moff[(size_t)i + 1] = moff[(size_t)i] + (int)members[i]->g.nblocks;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->mem + b->off_moff, moff.data(), moff.size() * sizeof(int), hipMemcpyHostToDevice,
+                           b->own);
     b->t_clock = t0;
     if (e == hipSuccess) e = hipStreamSynchronize(b->own);
     if (e != hipSuccess) {
@@ -979,6 +1008,15 @@ int eelbm_batch_advance(eelbm_batch* b, int64_t nsteps) {
         e = launch_clock_add(clock, t0 - b->t_clock, b->own);
         if (e != hipSuccess) return hip_fail(e, "batch clock launch");
         b->t_clock = t0;
+    }
+    if (b->active) {
+        // the work list of the members whose flags are set now
+        e = launch_batch_compact(b->active, reinterpret_cast<const int*>(b->mem + b->off_moff), (int)b->m.size(),
+                                 reinterpret_cast<int*>(b->mem + b->off_aoff),
+                                 reinterpret_cast<int*>(b->mem + b->off_count),
+                                 reinterpret_cast<const uint2*>(b->mem + b->off_work), b->nwork,
+                                 reinterpret_cast<uint2*>(b->mem + b->off_awork), b->own);
+        if (e != hipSuccess) return hip_fail(e, "batch work-list compaction");
     }
     int64_t left = nsteps;
     const int K = b->graph_steps;
@@ -1021,6 +1059,57 @@ int eelbm_batch_advance(eelbm_batch* b, int64_t nsteps) {
         h->diag_blocks = h->g.nblocks;
     }
     b->t_clock += nsteps;
+    return EELBM_OK;
+}
+
+int eelbm_batch_set_active(eelbm_batch* b, const int32_t* active) {
+    if (!b) return fail(EELBM_E_PARAM, "batch is NULL");
+    if ((active == nullptr) != (b->active == nullptr) && b->exec) {
+        // the captured launches read the full or the compacted work list
+        (void)hipStreamSynchronize(b->own);
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    b->active = active;
+    return EELBM_OK;
+}
+
+int eelbm_batch_rebuild_gated(eelbm_batch* b, int64_t t, const double* fields, const int32_t* gate) {
+    if (!b) return fail(EELBM_E_PARAM, "batch is NULL");
+    if (!fields || !gate) return fail(EELBM_E_PARAM, "fields or gate is NULL");
+    size_t off = 0;
+    for (size_t i = 0; i < b->m.size(); ++i) {
+        eelbm_handle* h = b->m[i];
+        const size_t n = (size_t)h->g.n;
+        const int D = h->g.D;
+        const double* f = fields + off;
+        int rc = init_impl(h, t, f, f + n, f + (1 + D) * n, f + (1 + 2 * D) * n, nullptr, 1, true, gate + i);
+        if (rc) return rc;
+        off += (size_t)(2 + 2 * D) * n;
+    }
+    return EELBM_OK;
+}
+
+int eelbm_batch_read_fields(eelbm_batch* b, float* out) {
+    if (!b) return fail(EELBM_E_PARAM, "batch is NULL");
+    if (!out) return fail(EELBM_E_PARAM, "out is NULL");
+    size_t off = 0;
+    for (size_t i = 0; i < b->m.size(); ++i) {
+        eelbm_handle* h = b->m[i];
+        const size_t n = (size_t)h->g.n;
+        const int D = h->g.D;
+        const double* mac = reinterpret_cast<const double*>(h->mem + h->L.macro);
+        // macro: alpha_g, alpha_l, u_g(D), u_l(D), dp_k -> alpha_g, u_g(D), u_l(D), dp_k
+        hipError_t e = launch_convert(mac, out + off, EELBM_DTYPE_F32, (long long)n, 0.0, 1.0, h->stream);
+        if (e == hipSuccess)
+            e = launch_convert(mac + 2 * n, out + off + n, EELBM_DTYPE_F32, (long long)(2 * D * n), 0.0, 1.0,
+                               h->stream);
+        if (e == hipSuccess)
+            e = launch_convert(mac + (2 + 2 * D) * n, out + off + (1 + 2 * D) * n, EELBM_DTYPE_F32, (long long)n, 0.0,
+                               1.0, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "convert launch");
+        off += (size_t)(2 + 2 * D) * n;
+    }
     return EELBM_OK;
 }
 

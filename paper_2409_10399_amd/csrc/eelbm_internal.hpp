@@ -67,6 +67,7 @@ struct KCtl {
     int refresh;          // lag refresh: t mod n_gamma == 0 (Eqs. (133), (137))
     int write_macro;
     int write_diag;
+    const int* gate;      // initialisation launches: skipped when *gate == 0 (device flag; NULL: run)
 };
 
 // One lattice of a batch: its parameters and its buffers for both parities
@@ -89,8 +90,10 @@ hipError_t launch_step(int lattice, int storage, int bc, bool init, const KParam
                        const KBuffers& b, const KCtl& c, dim3 grid, dim3 block, hipStream_t s);
 // one step of every lattice of a batch: grid = work items (lattice, tile)
 hipError_t launch_batch_step(int lattice, int storage, int bc, bool nts, const BatchLattice* lat, const uint2* work,
-                             long long nwork, const long long* clock, int k, int write_last, dim3 block,
-                             hipStream_t s);
+                             long long nwork, const long long* clock, int k, int write_last, const int* count,
+                             dim3 block, hipStream_t s);
+hipError_t launch_batch_compact(const int* active, const int* moff, int n, int* aoff, int* count, const uint2* work,
+                                long long nwork, uint2* awork, hipStream_t s);
 hipError_t launch_clock_add(long long* clock, long long add, hipStream_t s);
 hipError_t launch_sum(const double* x, long long n, double* partials, int nblocks, double* out,
                       hipStream_t s);

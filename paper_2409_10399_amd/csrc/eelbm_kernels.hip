@@ -1322,17 +1322,28 @@ __device__ __forceinline__ long long xcd_tile(long long id, long long nb, int re
 
 template <class L, class T, int BC, bool INIT, bool OUT, bool NTS>
 __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b, const KCtl ctl) {
+    if constexpr (INIT) {
+        // a gated rebuild: the whole grid skips it when the device flag is 0
+        if (ctl.gate && *ctl.gate == 0) return;
+    }
     step_body<L, T, BC, INIT, OUT, NTS>(p, b, ctl, xcd_tile(blockIdx.x, gridDim.x, p.xcd_remap), blockIdx.x);
 }
 
 // Batched step: one launch advances every lattice of a batch by one step.
 // Work item w = (lattice, tile); each lattice brings its own parameters and
 // both ping-pong buffer sets; the step's time is the batch clock + k + 1, so
-// a captured sequence of launches replays correctly at any time.
+// a captured sequence of launches replays correctly at any time.  count
+// (device, NULL: the whole grid): only the first *count work items are
+// taken -- the work list of the active lattices, compacted on the device
+// before the steps -- so that the active lattices' tiles spread over all
+// XCDs whatever lattices are left out; the other workgroups return at once.
 template <class L, class T, int BC, bool OUT, bool NTS>
 __global__ void __launch_bounds__(256) k_step_batch(const BatchLattice* lat, const uint2* work,
-                                                    const long long* clock, int k, int write_last) {
-    const uint2 w = work[xcd_tile(blockIdx.x, gridDim.x, 1)];
+                                                    const long long* clock, int k, int write_last,
+                                                    const int* count) {
+    const long long nb = count ? (long long)*count : (long long)gridDim.x;
+    if ((long long)blockIdx.x >= nb) return;
+    const uint2 w = work[xcd_tile(blockIdx.x, nb, 1)];
     const BatchLattice& d = lat[w.x];
     const KParams p = d.p;
     KCtl c;
@@ -1340,12 +1351,38 @@ __global__ void __launch_bounds__(256) k_step_batch(const BatchLattice* lat, con
     c.refresh = c.t % p.n_gamma == 0;
     c.write_macro = write_last;
     c.write_diag = write_last;
+    c.gate = nullptr;
     const KBuffers bb = d.buf[(c.t - 1) & 1];
     step_body<L, T, BC, false, OUT, NTS>(p, bb, c, w.y, w.y);
 }
 
 __global__ void k_clock_add(long long* clock, long long add) {
     if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] += add;
+}
+
+// Work list of the active lattices of a batch: aoff[i] = first position of
+// lattice i's tiles in the compacted list (the tiles of the active lattices
+// before it), *count = all active tiles.  moff[i] .. moff[i + 1] are lattice
+// i's positions in the full list.  One thread (a few hundred lattices).
+__global__ void k_batch_active_prefix(const int* __restrict__ active, const int* __restrict__ moff, int n,
+                                      int* __restrict__ aoff, int* __restrict__ count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int s = 0;
+        for (int i = 0; i < n; ++i) {
+            aoff[i] = s;
+            if (active[i]) s += moff[i + 1] - moff[i];
+        }
+        *count = s;
+    }
+}
+__global__ void k_batch_active_copy(const int* __restrict__ active, const int* __restrict__ moff,
+                                    const int* __restrict__ aoff, const uint2* __restrict__ work, long long nwork,
+                                    uint2* __restrict__ awork) {
+    for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < nwork;
+         j += (long long)gridDim.x * blockDim.x) {
+        const uint2 w = work[j];
+        if (active[w.x]) awork[aoff[w.x] + (j - moff[w.x])] = w;
+    }
 }
 
 // ---------------------------------------------------- small reductions
@@ -1494,18 +1531,19 @@ hipError_t launch_step(int lattice, int storage, int bc, bool init, const KParam
 
 template <class L, class T, bool OUT, bool NTS>
 static hipError_t gob_out(int bc, const BatchLattice* lat, const uint2* work, long long nwork,
-                          const long long* clock, int k, int write_last, dim3 block, hipStream_t s) {
+                          const long long* clock, int k, int write_last, const int* count, dim3 block,
+                          hipStream_t s) {
     const dim3 g((unsigned)nwork);
     const unsigned lds = window_bytes<L, T, false>(block);
     switch (bc) {
         case kBcPeriodic:
-            hipLaunchKernelGGL((k_step_batch<L, T, kBcPeriodic, OUT, NTS>), g, block, lds, s, lat, work, clock, k, write_last);
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcPeriodic, OUT, NTS>), g, block, lds, s, lat, work, clock, k, write_last, count);
             break;
         case kBcGeneric:
-            hipLaunchKernelGGL((k_step_batch<L, T, kBcGeneric, OUT, NTS>), g, block, lds, s, lat, work, clock, k, write_last);
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcGeneric, OUT, NTS>), g, block, lds, s, lat, work, clock, k, write_last, count);
             break;
         case kBcColumn:
-            hipLaunchKernelGGL((k_step_batch<L, T, kBcColumn, OUT, NTS>), g, block, lds, s, lat, work, clock, k, write_last);
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcColumn, OUT, NTS>), g, block, lds, s, lat, work, clock, k, write_last, count);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -1514,32 +1552,47 @@ static hipError_t gob_out(int bc, const BatchLattice* lat, const uint2* work, lo
 
 template <class L, class T>
 static hipError_t gob(int bc, bool nts, const BatchLattice* lat, const uint2* work, long long nwork,
-                      const long long* clock, int k, int write_last, dim3 block, hipStream_t s) {
+                      const long long* clock, int k, int write_last, const int* count, dim3 block, hipStream_t s) {
     if (nts)
-        return write_last ? gob_out<L, T, true, true>(bc, lat, work, nwork, clock, k, write_last, block, s)
-                          : gob_out<L, T, false, true>(bc, lat, work, nwork, clock, k, write_last, block, s);
-    return write_last ? gob_out<L, T, true, false>(bc, lat, work, nwork, clock, k, write_last, block, s)
-                      : gob_out<L, T, false, false>(bc, lat, work, nwork, clock, k, write_last, block, s);
+        return write_last ? gob_out<L, T, true, true>(bc, lat, work, nwork, clock, k, write_last, count, block, s)
+                          : gob_out<L, T, false, true>(bc, lat, work, nwork, clock, k, write_last, count, block, s);
+    return write_last ? gob_out<L, T, true, false>(bc, lat, work, nwork, clock, k, write_last, count, block, s)
+                      : gob_out<L, T, false, false>(bc, lat, work, nwork, clock, k, write_last, count, block, s);
 }
 
 template <class L>
 static hipError_t gob1(int storage, int bc, bool nts, const BatchLattice* lat, const uint2* work, long long nwork,
-                       const long long* clock, int k, int write_last, dim3 block, hipStream_t s) {
+                       const long long* clock, int k, int write_last, const int* count, dim3 block, hipStream_t s) {
     switch (storage) {
-        case EELBM_FP64: return gob<L, double>(bc, nts, lat, work, nwork, clock, k, write_last, block, s);
-        case EELBM_FP32: return gob<L, float>(bc, nts, lat, work, nwork, clock, k, write_last, block, s);
-        case EELBM_FP16: return gob<L, __half>(bc, nts, lat, work, nwork, clock, k, write_last, block, s);
-        case EELBM_BF16: return gob<L, __hip_bfloat16>(bc, nts, lat, work, nwork, clock, k, write_last, block, s);
+        case EELBM_FP64: return gob<L, double>(bc, nts, lat, work, nwork, clock, k, write_last, count, block, s);
+        case EELBM_FP32: return gob<L, float>(bc, nts, lat, work, nwork, clock, k, write_last, count, block, s);
+        case EELBM_FP16: return gob<L, __half>(bc, nts, lat, work, nwork, clock, k, write_last, count, block, s);
+        case EELBM_BF16:
+            return gob<L, __hip_bfloat16>(bc, nts, lat, work, nwork, clock, k, write_last, count, block, s);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_step(int lattice, int storage, int bc, bool nts, const BatchLattice* lat, const uint2* work,
-                             long long nwork, const long long* clock, int k, int write_last, dim3 block,
-                             hipStream_t s) {
-    if (lattice == EELBM_D2Q9) return gob1<D2Q9>(storage, bc, nts, lat, work, nwork, clock, k, write_last, block, s);
-    if (lattice == EELBM_D3Q19) return gob1<D3Q19>(storage, bc, nts, lat, work, nwork, clock, k, write_last, block, s);
+                             long long nwork, const long long* clock, int k, int write_last, const int* count,
+                             dim3 block, hipStream_t s) {
+    if (lattice == EELBM_D2Q9)
+        return gob1<D2Q9>(storage, bc, nts, lat, work, nwork, clock, k, write_last, count, block, s);
+    if (lattice == EELBM_D3Q19)
+        return gob1<D3Q19>(storage, bc, nts, lat, work, nwork, clock, k, write_last, count, block, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_compact(const int* active, const int* moff, int n, int* aoff, int* count, const uint2* work,
+                                long long nwork, uint2* awork, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_active_prefix, dim3(1), dim3(64), 0, s, active, moff, n, aoff, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    long long g = (nwork + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_batch_active_copy, dim3((unsigned)(g < 1 ? 1 : g)), dim3(256), 0, s, active, moff, aoff,
+                       work, nwork, awork);
+    return hipGetLastError();
 }
 
 hipError_t launch_clock_add(long long* clock, long long add, hipStream_t s) {

@@ -262,9 +262,15 @@ def _check_rc(rc):
 
 
 def rollout(net, lats, inst, cond, norm, t0, jumps, jump, defect_max, check_every, log, project=False):
-    """Surrogate rollout of all lattices together from their LBM state at t0
+    """Surrogate rollout of all lattices together from their LBM state at t0,
+    deciding on the host after every jump (it waits for the defects) and
+    advancing only the re-anchored lattices, in a batch built for them
     (project: each predicted jump is made to keep the gas-volume budget,
-    `conserve`, before its defect is judged)."""
+    `conserve`, before its defect is judged).  rollout_device gives the
+    same fields without waiting for the device; on the MI355X it is the
+    slower of the two (the host issues the steps of all lattices and the
+    gated rebuilds and reads of every lattice, and its launches, not the
+    device, set the pace), so the study times this one."""
     import torch
     from paper_2409_10399_amd import Batch
     from paper_2409_10399_amd.surrogate import apply_output, pack_input
@@ -304,6 +310,67 @@ def rollout(net, lats, inst, cond, norm, t0, jumps, jump, defect_max, check_ever
         t += jump
     torch.cuda.synchronize()
     return f, anchors, defects
+
+
+def rollout_device(net, lats, inst, cond, norm, t0, jumps, jump, defect_max, check_every, log, project=False,
+                   batch=None):
+    """Surrogate rollout of all lattices together from their LBM state at t0,
+    every decision taken on the device (no host wait inside the loop): per
+    jump the network's prediction, its gas-volume defects
+    (eelbm_cno_volume_defect), the re-anchoring mask (eelbm_cno_reanchor_policy),
+    gated rebuilds of the masked lattices whose LBM state is stale
+    (eelbm_batch_rebuild_gated), `jump` steps of one batch of all lattices
+    in which only the masked ones advance (eelbm_batch_set_active, the steps
+    replayed from a HIP graph), and the masked lattices' LBM fields
+    (eelbm_batch_read_fields) taken in place of the prediction
+    (eelbm_cno_select).  The same fields as
+    rollout.  project: see rollout (a host step: it is taken before the
+    defect, on the device tensors)."""
+    import torch
+    from paper_2409_10399_amd import Batch
+    from paper_2409_10399_amd.binding import lib
+    from paper_2409_10399_amd.surrogate import _p, _stream, apply_output, pack_input
+    L = lib()
+    N = len(lats)
+    ny, nx = inst[0][0]["ny"], inst[0][0]["nx"]
+    chi = diffusivities(inst)
+    f = torch.empty((N, 6, ny, nx), dtype=torch.float32, device="cuda")
+    for i, lat in enumerate(lats):
+        read_fields(lat, f[i])
+    valid = torch.ones(N, dtype=torch.int32, device="cuda")  # lattice i's LBM state equals f[i] at time t
+    mask = torch.zeros(N, dtype=torch.int32, device="cuda")
+    rebuild = torch.zeros(N, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    dfc = torch.empty(N, dtype=torch.float64, device="cuda")
+    lbm = torch.empty_like(f)
+    own = batch is None
+    if own:
+        batch = Batch(lats, tile=(64, 4), graph_steps=jump)
+    batch.set_active(mask)
+    t = t0
+    st = _stream()
+    for j in range(jumps):
+        x = pack_input(f, norm.mean, norm.inv, cond, net.cin)
+        pred = apply_output(f, net.forward(x, keep=False), norm.dscale)
+        if project:
+            conserve(f, pred, jump, chi)
+        _check_rc(L.eelbm_cno_volume_defect(_p(f), _p(pred), N, ny, nx, int(jump), _p(chi), _p(dfc), st))
+        force = int(check_every > 0 and (j + 1) % check_every == 0)
+        _check_rc(L.eelbm_cno_reanchor_policy(_p(dfc), N, float(defect_max), force, _p(valid), _p(mask),
+                                              _p(rebuild), _p(count), st))
+        fd = f.double()  # the planes of FIELD_PLANES are the rebuild layout
+        batch.rebuild_gated(t, fd, rebuild)
+        batch.advance(jump)
+        batch.read_fields(lbm)
+        _check_rc(L.eelbm_cno_select(_p(mask), N, 6 * ny * nx, _p(lbm), _p(pred), _p(pred), st))
+        f = pred
+        t += jump
+    torch.cuda.synchronize()
+    if own:
+        del batch
+    else:
+        batch.set_active(None)
+    return f, int(count.item()), []
 
 
 class JudgeSet:

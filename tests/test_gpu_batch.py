@@ -212,3 +212,97 @@ def test_batch_with_autotuned_tile():
         for a, b in zip(alone, batched):
             for k in FIELDS:
                 assert np.array_equal(a.read(k), b.read(k)), (n, k)
+
+
+def test_batch_active_flags_and_gated_rebuilds():
+    # members advance only where their device flag is set (also under graph
+    # replay, with the flags changed on the device between replays); a gated
+    # rebuild happens only where its device flag is set
+    import torch
+    from paper_2409_10399_amd import Batch
+    ws = members()
+    alone = _lattices(ws, "fp32")
+    batched = _lattices(ws, "fp32")
+    batch = Batch(batched, tile=(64, 4), graph_steps=4)
+    flags = torch.tensor([1, 0, 1, 0, 1], dtype=torch.int32, device="cuda")
+    batch.set_active(flags)
+    before = [{k: b.read(k) for k in FIELDS} for b in batched]
+    batch.advance(8)
+    for i, (a, b) in enumerate(zip(alone, batched)):
+        for k in FIELDS:
+            if flags[i]:
+                if k == FIELDS[0]:
+                    a.set_launch(64, 4)
+                    a.advance(8)
+                assert np.array_equal(a.read(k), b.read(k)), (i, k)
+            else:
+                assert np.array_equal(before[i][k], b.read(k)), (i, k)  # left as it was
+    # rebuild every member at t = 8 from other fields (the same channels
+    # advanced 3 steps), gated: the flag of members 1 and 3 is set, members
+    # 0, 2, 4 keep their state
+    t = batched[0].t
+    gate = torch.tensor([0, 1, 0, 1, 0], dtype=torch.int32, device="cuda")
+    src = _lattices(ws, "fp32")
+    for s_ in src:
+        s_.set_launch(64, 4)
+        s_.advance(3)  # other fields than the members hold
+    for i, (s_, b) in enumerate(zip(src, batched)):
+        f = {k: torch.tensor(s_.read(k), dtype=torch.float64, device="cuda") for k in ("alpha_g", "u_g", "u_l", "dp_k")}
+        b.reinit_fields_device(t, f, gate=gate[i:i + 1])
+        if gate[i]:
+            alone[i].reinit_fields_device(t, f)
+    flags.copy_(gate)  # now only the rebuilt members advance (graph replayed with the new flags)
+    batch.advance(4)
+    for i in (1, 3):
+        alone[i].advance(4)
+        for k in FIELDS:
+            assert np.array_equal(alone[i].read(k), batched[i].read(k)), (i, k)
+    # the members whose rebuild was gated off and which were inactive since
+    # still hold their fields of t = 8
+    for i in (0, 2, 4):
+        for k in FIELDS:
+            assert np.array_equal(alone[i].read(k), batched[i].read(k)), (i, k)
+
+
+def test_batch_rebuild_and_read_fields():
+    # the batch-level gated rebuild and field read equal the per-member calls
+    import torch
+    from paper_2409_10399_amd import Batch
+    ws = members()[:3]
+    a = _lattices(ws, "fp32")
+    b = _lattices(ws, "fp32")
+    for x in a + b:
+        x.set_launch(64, 4)
+        x.advance(5)
+    batch = Batch(b, tile=(64, 4))
+    src = _lattices(ws, "fp32")
+    planes = []
+    for s_ in src:
+        s_.set_launch(64, 4)
+        s_.advance(2)
+        planes.append(np.concatenate([s_.read("alpha_g")[None], s_.read("u_g"), s_.read("u_l"),
+                                      s_.read("dp_k")[None]]).ravel())
+    fields = torch.tensor(np.concatenate(planes), dtype=torch.float64, device="cuda")
+    gate = torch.tensor([1, 0, 1], dtype=torch.int32, device="cuda")
+    batch.rebuild_gated(5, fields, gate)
+    off = 0
+    for i, x in enumerate(a):
+        n = ws[i][0]["nx"] * ws[i][0]["ny"]
+        if gate[i]:
+            f = fields[off:off + 6 * n].view(6, -1)
+            x.reinit_fields_device(5, {"alpha_g": f[0], "u_g": f[1:3], "u_l": f[3:5], "dp_k": f[5]})
+        off += 6 * n
+    batch.advance(3)
+    for x in a:
+        x.advance(3)
+    out = torch.empty(off, dtype=torch.float32, device="cuda")
+    batch.read_fields(out)
+    got = out.cpu().numpy()
+    off = 0
+    for i, (x, y) in enumerate(zip(a, b)):
+        n = ws[i][0]["nx"] * ws[i][0]["ny"]
+        for k in FIELDS:
+            assert np.array_equal(x.read(k), y.read(k)), (i, k)
+        ref = np.concatenate([y.read("alpha_g")[None], y.read("u_g"), y.read("u_l"), y.read("dp_k")[None]]).ravel()
+        np.testing.assert_array_equal(got[off:off + 6 * n], ref.astype(np.float32))
+        off += 6 * n
