@@ -354,6 +354,15 @@ int eelbm_cno_conv_fwd(const float* in, int32_t B, int32_t H, int32_t W, int32_t
 int eelbm_cno_conv_fwd_cat(const float* src0, int32_t C0, int32_t up0, const float* src1, int32_t C1, int32_t B,
                            int32_t H, int32_t W, const uint16_t* wf, const float* bias, int32_t Cout, float* out,
                            int32_t act, float slope, void* stream);
+/* eelbm_cno_conv_fwd_cat with the activations of either side stored as BF16
+ * (uint16 bit patterns, round to nearest even) when in_bf16 / out_bf16 != 0,
+ * else FP32: src0 and src1 share the input type.  A BF16 output is the value
+ * the FP32 output would give rounded to BF16, i.e. exactly what the next
+ * convolution would have used; BF16 activations halve the traffic of
+ * inference passes. */
+int eelbm_cno_conv_fwd_cat_dt(const void* src0, int32_t C0, int32_t up0, const void* src1, int32_t C1, int32_t B,
+                              int32_t H, int32_t W, const uint16_t* wf, const float* bias, int32_t Cout, void* out,
+                              int32_t act, float slope, int32_t in_bf16, int32_t out_bf16, void* stream);
 /* Tile of the forward and input-gradient convolutions, process-wide: mt
  * M-tiles of 16 pixels per wavefront (1, 2 or 4) x nt N-tiles of 16 output
  * channels per workgroup (1..4); (0, 0) restores the automatic choice (two
@@ -412,6 +421,10 @@ int eelbm_cno_act_bwd(const float* y, const float* dy, int64_t n, float slope, f
  * (B, H, W, C) (in = that gradient, H, W the full sizes). */
 int eelbm_cno_pool(const float* in, int32_t B, int32_t H, int32_t W, int32_t C, float* out, int32_t backward,
                    void* stream);
+/* 2x2 average pooling forward of BF16 activations (uint16 bit patterns):
+ * the four values summed in FP32 in row order, times 1/4, rounded to BF16. */
+int eelbm_cno_pool_bf16(const uint16_t* in, int32_t B, int32_t H, int32_t W, int32_t C, uint16_t* out,
+                        void* stream);
 /* nearest 2x upsampling: forward (B, H, W, C) -> (B, 2H, 2W, C); backward:
  * the gradient of (B, 2H, 2W, C) summed back to (B, H, W, C). */
 int eelbm_cno_up(const float* in, int32_t B, int32_t H, int32_t W, int32_t C, float* out, int32_t backward,

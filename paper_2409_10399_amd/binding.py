@@ -78,6 +78,10 @@ SYMBOLS = {
     "eelbm_cno_conv_fwd_cat": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_int32,
                                        c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.c_float, c_void_p]),
     "eelbm_cno_conv_set_tile": (c_int, [c_int32, c_int32]),
+    "eelbm_cno_conv_fwd_cat_dt": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_int32, c_int32, c_int32, c_int32,
+                                          c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.c_float, c_int32,
+                                          c_int32, c_void_p]),
+    "eelbm_cno_pool_bf16": (c_int, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "eelbm_cno_volume_defect": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p,
                                         c_void_p]),
     "eelbm_cno_reanchor_policy": (c_int, [c_void_p, c_int32, ctypes.c_double, c_int32, c_void_p, c_void_p, c_void_p,

@@ -22,6 +22,7 @@
 #include <atomic>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "eelbm.h"
 #include "eelbm_internal.hpp"
@@ -93,11 +94,25 @@ struct ConvTile {
     static constexpr int kLdsB = 9 * 16 * NT * kPix;
 };
 
-template <int MT, int NT>
-__global__ void __launch_bounds__(256) k_conv2(const float* __restrict__ src0, int C0, int up0,
-                                              const float* __restrict__ src1, int C1, int B, int H, int W,
+// Activation storage: FP32, or BF16 (the bits of the rounded value; the
+// products round their operands to BF16 anyway, so a BF16 activation between
+// two convolutions is the value the next one would have used).
+struct ActF32 {
+    using S = float;
+    using V = f32x4;  // four channels as loaded
+};
+struct ActBF16 {
+    using S = unsigned short;
+    using V = uint2;
+};
+
+template <int MT, int NT, class AI, class AO>
+__global__ void __launch_bounds__(256) k_conv2(const typename AI::S* __restrict__ src0, int C0, int up0,
+                                              const typename AI::S* __restrict__ src1, int C1, int B, int H, int W,
                                               const unsigned short* __restrict__ wf, const float* __restrict__ bias,
-                                              int Cout, float* __restrict__ out, int act, float slope) {
+                                              int Cout, typename AO::S* __restrict__ out, int act, float slope) {
+    constexpr bool kInBf16 = std::is_same<AI, ActBF16>::value;
+    constexpr bool kOutBf16 = std::is_same<AO, ActBF16>::value;
     using T = ConvTile<MT, NT>;
     constexpr int LW = T::LW;
     __shared__ __attribute__((aligned(16))) unsigned short atile[T::kLdsA];
@@ -112,7 +127,7 @@ __global__ void __launch_bounds__(256) k_conv2(const float* __restrict__ src0, i
     const int Hs = up0 ? H / 2 : H, Ws = up0 ? W / 2 : W;
     const int kh = 8 * (lane >> 4);  // this lane's K offset within a chunk
 
-    f32x4 av[T::kAi];
+    typename AI::V av[T::kAi];
     u32x4 bv[T::kBi];
     // issue every global load of chunk c0 of tile `tile` (the values land in
     // av and, if withb, bv)
@@ -127,15 +142,15 @@ __global__ void __launch_bounds__(256) k_conv2(const float* __restrict__ src0, i
             const int lx = pix % LW, ly = pix / LW;
             const int yy = y0 - 1 + ly, xx = x0 - 1 + lx;
             const int c = c0 + 4 * g;
-            av[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+            av[i] = typename AI::V{};
             if (e < T::kA && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W && c < Cin) {
                 if (c < C0) {
                     const long long q = up0 ? ((long long)b * Hs + (yy >> 1)) * Ws + (xx >> 1)
                                             : ((long long)b * H + yy) * W + xx;
-                    av[i] = *reinterpret_cast<const f32x4*>(src0 + q * C0 + c);
+                    av[i] = *reinterpret_cast<const typename AI::V*>(src0 + q * C0 + c);
                 } else {
                     const long long q = ((long long)b * H + yy) * W + xx;
-                    av[i] = *reinterpret_cast<const f32x4*>(src1 + q * C1 + (c - C0));
+                    av[i] = *reinterpret_cast<const typename AI::V*>(src1 + q * C1 + (c - C0));
                 }
             }
         }
@@ -156,7 +171,12 @@ __global__ void __launch_bounds__(256) k_conv2(const float* __restrict__ src0, i
 #pragma unroll
         for (int i = 0; i < T::kAi; ++i) {
             const int e = threadIdx.x + 256 * i;
-            if (e < T::kA) *reinterpret_cast<s16x4*>(atile + (e >> 3) * kPix + 4 * (e & 7)) = pack4(av[i]);
+            if (e < T::kA) {
+                if constexpr (kInBf16)
+                    *reinterpret_cast<uint2*>(atile + (e >> 3) * kPix + 4 * (e & 7)) = av[i];
+                else
+                    *reinterpret_cast<s16x4*>(atile + (e >> 3) * kPix + 4 * (e & 7)) = pack4(av[i]);
+            }
         }
         if (!withb) return;
 #pragma unroll
@@ -221,7 +241,12 @@ __global__ void __launch_bounds__(256) k_conv2(const float* __restrict__ src0, i
                             const int px = xt * T::TW + 16 * m + 4 * (lane >> 4) + t;
                             float v = acc[m][j][t] + bc;
                             v = (act && v < 0.f) ? slope * v : v;
-                            if (px < W) out[(((long long)b * H + y) * W + px) * Cout + co] = v;
+                            if (px < W) {
+                                if constexpr (kOutBf16)
+                                    out[(((long long)b * H + y) * W + px) * Cout + co] = bf16_bits(v);
+                                else
+                                    out[(((long long)b * H + y) * W + px) * Cout + co] = v;
+                            }
                         }
                     }
                 }
@@ -340,6 +365,23 @@ __global__ void k_pool_fwd(const float* __restrict__ in, int B, int H, int W, in
         const int b = (int)(r / (H / 2));
         const float* s = in + (((long long)b * H + 2 * y) * W + 2 * x) * C + c;
         out[i] = 0.25f * (s[0] + s[C] + s[(long long)W * C] + s[(long long)W * C + C]);
+    }
+}
+// the same pooling of BF16 activations (sum in FP32 in the order above,
+// rounded to BF16)
+__global__ void k_pool_fwd_bf16(const unsigned short* __restrict__ in, int B, int H, int W, int C,
+                                unsigned short* __restrict__ out) {
+    const long long n = (long long)B * (H / 2) * (W / 2) * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        long long r = i / C;
+        const int x = (int)(r % (W / 2));
+        r /= (W / 2);
+        const int y = (int)(r % (H / 2));
+        const int b = (int)(r / (H / 2));
+        const unsigned short* s = in + (((long long)b * H + 2 * y) * W + 2 * x) * C + c;
+        out[i] = bf16_bits(0.25f * (bf16_float(s[0]) + bf16_float(s[C]) + bf16_float(s[(long long)W * C]) +
+                                    bf16_float(s[(long long)W * C + C])));
     }
 }
 __global__ void k_pool_bwd(const float* __restrict__ dout, int B, int H, int W, int C, float* __restrict__ din) {
@@ -652,9 +694,10 @@ int cu_count() {
 
 // forward tiling: MT M-tiles of 16 pixels per wavefront (1, 2 or 4) and NT
 // output tiles of 16 channels per workgroup (1 to 4, dividing Cout / 16)
-template <int MT, int NT>
-void conv2_mn(const float* src0, int C0, int up0, const float* src1, int C1, int B, int H, int W,
-              const unsigned short* wf, const float* bias, int Cout, float* out, int act, float slope, hipStream_t s) {
+template <int MT, int NT, class AI, class AO>
+void conv2_mn(const typename AI::S* src0, int C0, int up0, const typename AI::S* src1, int C1, int B, int H, int W,
+              const unsigned short* wf, const float* bias, int Cout, typename AO::S* out, int act, float slope,
+              hipStream_t s) {
     // at most as many workgroups as fit on the chip at once (LDS-bound), each
     // looping over its share of the tiles
     const long long tiles = (long long)B * ((H + kRows - 1) / kRows) * ((W + 16 * MT - 1) / (16 * MT));
@@ -662,26 +705,43 @@ void conv2_mn(const float* src0, int C0, int up0, const float* src1, int C1, int
     static std::atomic<int> per_cu{0};  // workgroups of this kernel one compute unit holds (LDS, registers)
     int pc = per_cu.load();
     if (pc <= 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, reinterpret_cast<const void*>(&k_conv2<MT, NT>), 256,
-                                                         0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &pc, reinterpret_cast<const void*>(&k_conv2<MT, NT, AI, AO>), 256, 0) != hipSuccess ||
             pc <= 0)
             pc = 1;
         per_cu.store(pc);
     }
     const long long resident = std::max(1ll, (long long)cu_count() * pc / ngroups);
     const dim3 g((unsigned)std::min(tiles, resident), (unsigned)ngroups);
-    hipLaunchKernelGGL((k_conv2<MT, NT>), g, dim3(256), 0, s, src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out,
-                       act, slope);
+    hipLaunchKernelGGL((k_conv2<MT, NT, AI, AO>), g, dim3(256), 0, s, src0, C0, up0, src1, C1, B, H, W, wf, bias,
+                       Cout, out, act, slope);
 }
-template <int MT>
-void conv2_m(int nt, const float* src0, int C0, int up0, const float* src1, int C1, int B, int H, int W,
-             const unsigned short* wf, const float* bias, int Cout, float* out, int act, float slope, hipStream_t s) {
+template <int MT, class AI, class AO>
+void conv2_m(int nt, const typename AI::S* src0, int C0, int up0, const typename AI::S* src1, int C1, int B, int H,
+             int W, const unsigned short* wf, const float* bias, int Cout, typename AO::S* out, int act, float slope,
+             hipStream_t s) {
     switch (nt) {
-        case 1: conv2_mn<MT, 1>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
-        case 2: conv2_mn<MT, 2>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
-        case 3: conv2_mn<MT, 3>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
-        default: conv2_mn<MT, 4>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
+        case 1: conv2_mn<MT, 1, AI, AO>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
+        case 2: conv2_mn<MT, 2, AI, AO>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
+        case 3: conv2_mn<MT, 3, AI, AO>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
+        default: conv2_mn<MT, 4, AI, AO>(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, s); break;
     }
+}
+template <class AI, class AO>
+void conv2_launch(int mt, int nt, const void* src0, int C0, int up0, const void* src1, int C1, int B, int H, int W,
+                  const unsigned short* wf, const float* bias, int Cout, void* out, int act, float slope,
+                  hipStream_t s) {
+    using SI = typename AI::S;
+    using SO = typename AO::S;
+    const SI* a = static_cast<const SI*>(src0);
+    const SI* b = static_cast<const SI*>(src1);
+    SO* o = static_cast<SO*>(out);
+    if (mt == 4)
+        conv2_m<4, AI, AO>(nt, a, C0, up0, b, C1, B, H, W, wf, bias, Cout, o, act, slope, s);
+    else if (mt == 2)
+        conv2_m<2, AI, AO>(nt, a, C0, up0, b, C1, B, H, W, wf, bias, Cout, o, act, slope, s);
+    else
+        conv2_m<1, AI, AO>(nt, a, C0, up0, b, C1, B, H, W, wf, bias, Cout, o, act, slope, s);
 }
 // Automatic tile, from a sweep of every tile over the layers of two U-Nets
 // (widths 32/48/96/192 and 16/32/64/128, batch 8 x 256^2) on the MI355X:
@@ -729,9 +789,9 @@ bool shape_ok(int B, int H, int W, int Cin, int Cout) {
 
 extern "C" {
 
-int eelbm_cno_conv_fwd_cat(const float* src0, int32_t C0, int32_t up0, const float* src1, int32_t C1, int32_t B,
-                           int32_t H, int32_t W, const uint16_t* wf, const float* bias, int32_t Cout, float* out,
-                           int32_t act, float slope, void* stream) {
+int eelbm_cno_conv_fwd_cat_dt(const void* src0, int32_t C0, int32_t up0, const void* src1, int32_t C1, int32_t B,
+                              int32_t H, int32_t W, const uint16_t* wf, const float* bias, int32_t Cout, void* out,
+                              int32_t act, float slope, int32_t in_bf16, int32_t out_bf16, void* stream) {
     if (!src0 || !wf || !out || C0 <= 0 || C0 % 16 != 0 || C1 < 0 || C1 % 16 != 0 || (C1 > 0 && !src1) ||
         !shape_ok(B, H, W, C0 + C1, Cout))
         return EELBM_E_PARAM;
@@ -748,12 +808,29 @@ int eelbm_cno_conv_fwd_cat(const float* src0, int32_t C0, int32_t up0, const flo
         conv2_tile(W, Cout, &mt, &nt);
     else if ((Cout / 16) % nt != 0)
         return EELBM_E_PARAM;
-    if (mt == 4)
-        conv2_m<4>(nt, src0, C0, up0, src1, C1, B, H, W, w, bias, Cout, out, act, slope, s);
-    else if (mt == 2)
-        conv2_m<2>(nt, src0, C0, up0, src1, C1, B, H, W, w, bias, Cout, out, act, slope, s);
+    if (in_bf16 && out_bf16)
+        conv2_launch<ActBF16, ActBF16>(mt, nt, src0, C0, up0, src1, C1, B, H, W, w, bias, Cout, out, act, slope, s);
+    else if (in_bf16)
+        conv2_launch<ActBF16, ActF32>(mt, nt, src0, C0, up0, src1, C1, B, H, W, w, bias, Cout, out, act, slope, s);
+    else if (out_bf16)
+        conv2_launch<ActF32, ActBF16>(mt, nt, src0, C0, up0, src1, C1, B, H, W, w, bias, Cout, out, act, slope, s);
     else
-        conv2_m<1>(nt, src0, C0, up0, src1, C1, B, H, W, w, bias, Cout, out, act, slope, s);
+        conv2_launch<ActF32, ActF32>(mt, nt, src0, C0, up0, src1, C1, B, H, W, w, bias, Cout, out, act, slope, s);
+    return last_rc(hipGetLastError());
+}
+
+int eelbm_cno_conv_fwd_cat(const float* src0, int32_t C0, int32_t up0, const float* src1, int32_t C1, int32_t B,
+                           int32_t H, int32_t W, const uint16_t* wf, const float* bias, int32_t Cout, float* out,
+                           int32_t act, float slope, void* stream) {
+    return eelbm_cno_conv_fwd_cat_dt(src0, C0, up0, src1, C1, B, H, W, wf, bias, Cout, out, act, slope, 0, 0, stream);
+}
+
+int eelbm_cno_pool_bf16(const uint16_t* in, int32_t B, int32_t H, int32_t W, int32_t C, uint16_t* out,
+                        void* stream) {
+    if (!in || !out || B < 1 || H < 2 || W < 2 || C < 1 || (H & 1) || (W & 1)) return EELBM_E_PARAM;
+    hipLaunchKernelGGL(k_pool_fwd_bf16, dim3(grid_for((long long)B * H * W * C / 4)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), reinterpret_cast<const unsigned short*>(in), B, H, W, C,
+                       reinterpret_cast<unsigned short*>(out));
     return last_rc(hipGetLastError());
 }
 

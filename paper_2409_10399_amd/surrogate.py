@@ -100,12 +100,12 @@ class CNO:
         return [(w.double().cpu().numpy(), b.double().cpu().numpy()) for w, b in zip(self.W, self.b)]
 
     # ------------------------------------------------------------ buffers
-    def _buf(self, name, shape):
+    def _buf(self, name, shape, bf16=False):
         import torch
-        key = (name, tuple(shape))
+        key = (name, tuple(shape), bf16)
         t = self._bufs.get(key)
         if t is None:
-            t = torch.empty(shape, dtype=torch.float32, device="cuda")
+            t = torch.empty(shape, dtype=torch.int16 if bf16 else torch.float32, device="cuda")
             self._bufs[key] = t
         return t
 
@@ -114,6 +114,42 @@ class CNO:
         B, H, W, ci = x.shape
         _check(lib().eelbm_cno_conv_fwd(_p(x), B, H, W, ci, _p(self.wf[li]), _p(self.b[li]), out.shape[3], _p(out),
                                         int(act), self.slope, _stream()))
+
+    def infer(self, x):
+        """Inference forward pass with BF16 activations between the layers
+        (the first layer reads the FP32 input x, the last writes FP32): the
+        products round their operands to BF16 anyway, so only the pooling
+        sees rounded inputs; half the activation traffic of forward()."""
+        L, st = lib(), _stream()
+        B, H, W, _ = x.shape
+        nl, wd = len(self.widths), self.widths
+        conv = L.eelbm_cno_conv_fwd_cat_dt
+        h, li, hb = x, 0, 0
+        for k in range(nl):
+            Hk, Wk = H >> k, W >> k
+            for j in range(2):
+                out = self._buf(f"e{k}_{j}", (B, Hk, Wk, wd[k]), True)
+                _check(conv(_p(h), h.shape[3], 0, None, 0, B, Hk, Wk, _p(self.wf[li]), _p(self.b[li]), wd[k],
+                            _p(out), 1, self.slope, hb, 1, st))
+                h, li, hb = out, li + 1, 1
+            if k < nl - 1:
+                p = self._buf(f"p{k + 1}", (B, Hk // 2, Wk // 2, wd[k]), True)
+                _check(L.eelbm_cno_pool_bf16(_p(h), B, Hk, Wk, wd[k], _p(p), st))
+                h = p
+        for k in range(nl - 2, -1, -1):
+            Hk, Wk = H >> k, W >> k
+            skip = self._buf(f"e{k}_1", (B, Hk, Wk, wd[k]), True)
+            d1 = self._buf(f"d{k}_1", (B, Hk, Wk, wd[k]), True)
+            _check(conv(_p(h), wd[k + 1], 1, None, 0, B, Hk, Wk, _p(self.wf[li]), _p(self.b[li]), wd[k], _p(d1), 1,
+                        self.slope, 1, 1, st))
+            d2 = self._buf(f"d{k}_2", (B, Hk, Wk, wd[k]), True)
+            _check(conv(_p(d1), wd[k], 0, _p(skip), wd[k], B, Hk, Wk, _p(self.wf[li + 1]), _p(self.b[li + 1]), wd[k],
+                        _p(d2), 1, self.slope, 1, 1, st))
+            h, li = d2, li + 2
+        out = self._buf("out", (B, H, W, self.cout))
+        _check(conv(_p(h), wd[0], 0, None, 0, B, H, W, _p(self.wf[li]), _p(self.b[li]), self.cout, _p(out), 0,
+                    self.slope, 1, 0, st))
+        return out
 
     def forward(self, x, keep=True):
         """x: (B, H, W, cin) FP32 contiguous device tensor (H, W divisible by
@@ -269,7 +305,9 @@ def apply_output(fields, net_out, dscale):
 def _time_forward():
     """Time the forward pass of a randomly initialised network on a random
     NHWC input with HIP events: python -m paper_2409_10399_amd.surrogate
-    [--widths 32,48,96,192] [--batch 8] [--grid 256] [--reps 20]."""
+    [--widths 32,48,96,192] [--batch 8] [--grid 256] [--reps 20] [--fp32]
+    (the inference pass with BF16 activations; --fp32: forward() with FP32
+    activations, as in training)."""
     import argparse
     import json
 
@@ -279,21 +317,24 @@ def _time_forward():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--fp32", action="store_true")
     a = ap.parse_args()
     net = CNO(9, 6, [int(w) for w in a.widths.split(",")], seed=0)
     x = torch.randn(a.batch, a.grid, a.grid, net.cin, device="cuda")
+    run = (lambda: net.forward(x, keep=False)) if a.fp32 else (lambda: net.infer(x))
     for _ in range(3):
-        net.forward(x, keep=False)
+        run()
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(st)
     for _ in range(a.reps):
-        net.forward(x, keep=False)
+        run()
     e1.record(st)
     torch.cuda.synchronize()
     print(json.dumps({"widths": net.widths, "params": net.n_params, "batch": a.batch, "grid": a.grid,
-                      "ms_per_forward": e0.elapsed_time(e1) / a.reps}), flush=True)
+                      "activations": "fp32" if a.fp32 else "bf16", "ms_per_forward": e0.elapsed_time(e1) / a.reps}),
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -286,7 +286,7 @@ def rollout(net, lats, inst, cond, norm, t0, jumps, jump, defect_max, check_ever
     defects = []
     for j in range(jumps):
         x = pack_input(f, norm.mean, norm.inv, cond, net.cin)
-        pred = apply_output(f, net.forward(x, keep=False), norm.dscale)
+        pred = apply_output(f, net.infer(x), norm.dscale)
         if project:
             conserve(f, pred, jump, chi)
         dfc = defect(f, pred, jump, chi)
@@ -351,7 +351,7 @@ def rollout_device(net, lats, inst, cond, norm, t0, jumps, jump, defect_max, che
     st = _stream()
     for j in range(jumps):
         x = pack_input(f, norm.mean, norm.inv, cond, net.cin)
-        pred = apply_output(f, net.forward(x, keep=False), norm.dscale)
+        pred = apply_output(f, net.infer(x), norm.dscale)
         if project:
             conserve(f, pred, jump, chi)
         _check_rc(L.eelbm_cno_volume_defect(_p(f), _p(pred), N, ny, nx, int(jump), _p(chi), _p(dfc), st))
@@ -492,8 +492,8 @@ def measure_saved(prefix, log=lambda m: None, reps=3):
     net, norm, meta = load_model(prefix)
     ts = JudgeSet(meta["test_seed"], meta["test_inst"], meta["grid"], meta["t0"], meta["jumps"], meta["jump"], log)
     pol = meta["chosen_policy"]
-    net.forward(__import__("torch").zeros((len(ts.lats), meta["grid"], meta["grid"], net.cin), device="cuda"),
-                keep=False)  # warm-up
+    x0 = __import__("torch").zeros((len(ts.lats), meta["grid"], meta["grid"], net.cin), device="cuda")
+    net.infer(x0)  # warm-up
     out = {"chosen": ts.judge(net, norm, pol["defect_max"], pol["check_every"], log, reps=reps),
            "specified": ts.judge(net, norm, 1e-3, 5, log, reps=reps), "test_screened": ts.screened}
     return out, meta
@@ -526,6 +526,7 @@ def main():
     ap.add_argument("--out", default="")
     ap.add_argument("--save", default="", help="prefix of the saved model (.npz weights, .json policy and meta)")
     ap.add_argument("--load", default="", help="a saved model: skip training and validation, judge on test")
+    ap.add_argument("--revalidate", action="store_true", help="with --load: choose the policy again on validation")
     ap.add_argument("--policies", default="",
                     help="re-anchoring policies judged on the validation channels, "
                          "'defect_max:check_every[:p],...' (p: predicted jumps keep the gas-volume budget)")
@@ -536,6 +537,34 @@ def main():
     def log(m):
         print(m, flush=True)
 
+    if a.load and a.revalidate:
+        # the saved network's policy chosen again on its validation channels
+        # (e.g. after a change of the inference arithmetic), then the test
+        # channels judged once; the model's json is rewritten under --save
+        net, norm, meta = load_model(a.load)
+        vs = JudgeSet(meta["val_seed"], meta["val_inst"], meta["grid"], meta["t0"], meta["jumps"], meta["jump"], log)
+        net.infer(torch.zeros((len(vs.lats), meta["grid"], meta["grid"], net.cin), device="cuda"))  # warm-up
+        table = []
+        for dmax, chk in DEFAULT_POLICIES:
+            r = vs.judge(net, norm, dmax, chk, log)
+            table.append(r)
+            log(f"# validation, policy {dmax:g}:{chk}: rel-L2 max {r['rel_l2_alpha_max']:.4f}; re-anchored "
+                f"{r['anchors']}; speedup {r['speedup']:.2f}")
+        best = choose_policy(table, meta["val_target"]) or min(table, key=lambda r: r["rel_l2_alpha_max"])
+        meta["chosen_policy"] = {"defect_max": best["defect_max"], "check_every": best["check_every"]}
+        meta["validation"] = [{k: r[k] for k in ("defect_max", "check_every", "rel_l2_alpha_max", "rel_l2_alpha_mean",
+                                                  "anchors", "speedup")} for r in table]
+        meta["revalidated"] = "python -m paper_2409_10399_amd.surrogate_study " + " ".join(sys.argv[1:])
+        del vs
+        ts = JudgeSet(meta["test_seed"], meta["test_inst"], meta["grid"], meta["t0"], meta["jumps"], meta["jump"], log)
+        for name, (dmax, chk) in (("chosen", (best["defect_max"], best["check_every"])), ("specified", (1e-3, 5))):
+            r = ts.judge(net, norm, dmax, chk, log, reps=3)
+            log(f"# test, {name} policy {dmax:g}:{chk}: rel-L2 max {r['rel_l2_alpha_max']:.4f}, re-anchored "
+                f"{r['anchors']}/{r['jumps']}, speedup {r['speedup']:.2f}")
+        if a.save:
+            with open(a.save + ".json", "w") as fh:
+                json.dump(meta, fh, indent=1)
+        return
     if a.load:
         res, meta = measure_saved(a.load, log)
         for k in ("chosen", "specified"):
@@ -585,7 +614,7 @@ def main():
     # ---- policy chosen on validation channels (their own seed), then judged
     # once on the test channels
     vs = JudgeSet(a.val_seed, a.val_inst, a.grid, a.t0, a.jumps, a.jump, log)
-    net.forward(torch.zeros((len(vs.lats), a.grid, a.grid, net.cin), device="cuda"), keep=False)  # warm-up
+    net.infer(torch.zeros((len(vs.lats), a.grid, a.grid, net.cin), device="cuda"))  # warm-up
     pols = DEFAULT_POLICIES if not a.policies else [
         (float(x.split(":")[0]), int(x.split(":")[1])) for x in a.policies.split(",") if x]
     table = []

@@ -305,3 +305,76 @@ def test_training_steps_reduce_loss():
         net.backward(net.dloss)
         net.adam(3e-3)
     assert np.isfinite(losses).all() and losses[-1] < 0.5 * losses[0], losses[::10]
+
+
+def _bf16_bits(a):
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+    return (((u + np.uint32(0x7FFF) + ((u >> 16) & np.uint32(1))) >> 16) & np.uint32(0xFFFF)).astype(np.uint16)
+
+
+def _bits_to_f32(b):
+    return (b.astype(np.uint32) << 16).view(np.float32)
+
+
+@pytest.mark.parametrize("in_bf16,out_bf16", [(1, 1), (0, 1), (1, 0)])
+def test_bf16_activation_conv_equals_rounded_fp32(in_bf16, out_bf16):
+    """BF16 activations: with inputs that BF16 holds exactly, the convolution
+    reading BF16 and/or writing BF16 gives the FP32 path's values, rounded to
+    BF16 where the output is BF16 -- bit for bit (the fused upsample and
+    concatenation included)."""
+    import torch
+    from paper_2409_10399_amd.binding import lib
+    from paper_2409_10399_amd.surrogate import _p, _stream
+    B, Hs, Ws, c0, c1, co = 2, 10, 36, 48, 32, 96
+    H, W = 2 * Hs, 2 * Ws
+    rng = np.random.default_rng(in_bf16 + 2 * out_bf16)
+    h = _bits_to_f32(_bf16_bits(rng.normal(size=(B, Hs, Ws, c0))))
+    skip = _bits_to_f32(_bf16_bits(rng.normal(size=(B, H, W, c1))))
+    ci = c0 + c1
+    w = (rng.normal(size=(9, ci, co)) / np.sqrt(9 * ci)).astype(np.float32)
+    L, st = lib(), _stream()
+    dw_ = dev(w)
+    wf = torch.empty(w.size, dtype=torch.int16, device="cuda")
+    wd = torch.empty(w.size, dtype=torch.int16, device="cuda")
+    assert L.eelbm_cno_pack_weights(_p(dw_), ci, co, _p(wf), _p(wd), st) == 0
+    db_ = dev(rng.normal(size=co).astype(np.float32))
+    ref = torch.empty((B, H, W, co), dtype=torch.float32, device="cuda")
+    assert L.eelbm_cno_conv_fwd_cat(_p(dev(h)), c0, 1, _p(dev(skip)), c1, B, H, W, _p(wf), _p(db_), co, _p(ref), 1,
+                                    0.1, st) == 0
+    if in_bf16:
+        sh = torch.tensor(_bf16_bits(h).view(np.int16), device="cuda")
+        ss = torch.tensor(_bf16_bits(skip).view(np.int16), device="cuda")
+    else:
+        sh, ss = dev(h), dev(skip)
+    out = torch.empty((B, H, W, co), dtype=torch.int16 if out_bf16 else torch.float32, device="cuda")
+    assert L.eelbm_cno_conv_fwd_cat_dt(_p(sh), c0, 1, _p(ss), c1, B, H, W, _p(wf), _p(db_), co, _p(out), 1, 0.1,
+                                       in_bf16, out_bf16, st) == 0
+    r = ref.cpu().numpy()
+    if out_bf16:
+        assert np.array_equal(out.cpu().numpy().view(np.uint16), _bf16_bits(r))
+    else:
+        assert np.array_equal(out.cpu().numpy(), r)
+
+
+def test_bf16_pool_and_inference_pass():
+    """2x2 pooling of BF16 activations against the same sum in FP32 rounded
+    to BF16; the inference pass (BF16 activations) against forward() (FP32
+    activations), which it differs from only where pooling sees rounded
+    inputs."""
+    import torch
+    from paper_2409_10399_amd.binding import lib
+    from paper_2409_10399_amd.surrogate import CNO, _p, _stream
+    rng = np.random.default_rng(4)
+    B, H, W, C = 2, 12, 20, 32
+    x = _bf16_bits(rng.normal(size=(B, H, W, C)))
+    xf = _bits_to_f32(x)
+    out = torch.empty((B, H // 2, W // 2, C), dtype=torch.int16, device="cuda")
+    assert lib().eelbm_cno_pool_bf16(_p(torch.tensor(x.view(np.int16), device="cuda")), B, H, W, C, _p(out),
+                                     _stream()) == 0
+    s = ((xf[:, 0::2, 0::2] + xf[:, 0::2, 1::2]) + xf[:, 1::2, 0::2]) + xf[:, 1::2, 1::2]
+    assert np.array_equal(out.cpu().numpy().view(np.uint16), _bf16_bits(np.float32(0.25) * s))
+    net = CNO(9, 6, [16, 32, 48], seed=3)
+    xin = torch.randn((2, 64, 64, net.cin), device="cuda")
+    a = net.forward(xin, keep=False).clone()
+    b = net.infer(xin).clone()
+    assert float((a - b).norm() / a.norm()) < 1e-2
