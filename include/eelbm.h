@@ -343,7 +343,8 @@ int eelbm_autotune(eelbm_handle* h, int32_t steps, int32_t force, int32_t* tile_
 
 /* out = act(conv3x3(in; Wf) + bias), zero padding; act = leaky-ReLU with
  * `slope` if act != 0; bias may be NULL.  The weight copy (9 * Cin * Cout)
- * must hold fewer than 2^31 values (EELBM_E_PARAM otherwise). */
+ * and the input and output tensors must each hold fewer than 2^31 values
+ * (EELBM_E_PARAM otherwise). */
 int eelbm_cno_conv_fwd(const float* in, int32_t B, int32_t H, int32_t W, int32_t Cin, const uint16_t* wf,
                        const float* bias, int32_t Cout, float* out, int32_t act, float slope, void* stream);
 /* The same convolution of the channel concatenation [src0 | src1] (C0 + C1

@@ -129,29 +129,55 @@ __global__ void __launch_bounds__(256) k_conv2(const typename AI::S* __restrict_
 
     typename AI::V av[T::kAi];
     u32x4 bv[T::kBi];
-    // issue every global load of chunk c0 of tile `tile` (the values land in
-    // av and, if withb, bv)
-    auto load = [&](int tile, int c0, bool withb) {
-        const int xt = tile % gx, r = tile / gx;
-        const int yt = r % gy, b = r / gy;
-        const int x0 = xt * T::TW, y0 = yt * kRows;
+    // this thread's pixels of the staged window (tile-invariant): pixel
+    // (e >> 3) of the window, e = threadIdx.x + 256 i, as ly << 16 | lx
+    int lxy[T::kAi];
+#pragma unroll
+    for (int i = 0; i < T::kAi; ++i) {
+        const int pix = (int)(threadIdx.x >> 3) + 32 * i;
+        lxy[i] = (pix / LW) << 16 | (pix % LW);
+    }
+    const int g4 = 4 * (int)(threadIdx.x & 7);  // this thread's channel group within a chunk
+    // tile coordinates, advanced by gridDim.x tiles at a time without
+    // division: G = gridDim.x = (Gb gy + Gy) gx + Gx
+    const int G = (int)gridDim.x;
+    const int Gx = G % gx, Gy = (G / gx) % gy, Gb = G / (gx * gy);
+    struct TileXY {
+        int x, y, b;
+    };
+    auto next_tile = [&](TileXY t) {
+        t.x += Gx;
+        int cy = 0;
+        if (t.x >= gx) {
+            t.x -= gx;
+            cy = 1;
+        }
+        t.y += Gy + cy;
+        int cb = 0;
+        if (t.y >= gy) {
+            t.y -= gy;
+            cb = 1;
+        }
+        t.b += Gb + cb;
+        return t;
+    };
+    // issue every global load of chunk c0 of tile t (the values land in av
+    // and, if withb, bv); element offsets fit in 32 bits (host check)
+    auto load = [&](TileXY t, int c0, bool withb) {
+        const int x0 = t.x * T::TW - 1, y0 = t.y * kRows - 1;
+        const int c = c0 + g4;
+        const bool in0 = c < C0, inc = c < Cin;
+        const typename AI::S* base = in0 ? src0 + c : (inc ? src1 + (c - C0) : src0);
+        const int cs = in0 ? C0 : C1;
 #pragma unroll
         for (int i = 0; i < T::kAi; ++i) {
-            const int e = threadIdx.x + 256 * i;
-            const int g = e & 7, pix = e >> 3;
-            const int lx = pix % LW, ly = pix / LW;
-            const int yy = y0 - 1 + ly, xx = x0 - 1 + lx;
-            const int c = c0 + 4 * g;
+            const int e = (int)threadIdx.x + 256 * i;
+            const int yy = y0 + (lxy[i] >> 16), xx = x0 + (lxy[i] & 0xffff);
             av[i] = typename AI::V{};
-            if (e < T::kA && (unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W && c < Cin) {
-                if (c < C0) {
-                    const long long q = up0 ? ((long long)b * Hs + (yy >> 1)) * Ws + (xx >> 1)
-                                            : ((long long)b * H + yy) * W + xx;
-                    av[i] = *reinterpret_cast<const typename AI::V*>(src0 + q * C0 + c);
-                } else {
-                    const long long q = ((long long)b * H + yy) * W + xx;
-                    av[i] = *reinterpret_cast<const typename AI::V*>(src1 + q * C1 + (c - C0));
-                }
+            if ((T::kA % 256 == 0 || i + 1 < T::kAi || e < T::kA) && (unsigned)yy < (unsigned)H &&
+                (unsigned)xx < (unsigned)W && inc) {
+                const int q = (in0 && up0) ? (t.b * Hs + (yy >> 1)) * Ws + (xx >> 1) : (t.b * H + yy) * W + xx;
+                av[i] = *reinterpret_cast<const typename AI::V*>(base + q * cs);
             }
         }
         if (!withb) return;
@@ -163,7 +189,7 @@ __global__ void __launch_bounds__(256) k_conv2(const typename AI::S* __restrict_
             const int k = c0 + 8 * g;
             bv[i] = u32x4{0u, 0u, 0u, 0u};
             if (e < T::kB && k < Cin)
-                bv[i] = *reinterpret_cast<const u32x4*>(wf + (long long)(n0 + col) * K + tap * Cin + k);
+                bv[i] = *reinterpret_cast<const u32x4*>(wf + (n0 + col) * K + tap * Cin + k);
         }
     };
     // write the loaded chunk to LDS
@@ -191,7 +217,8 @@ __global__ void __launch_bounds__(256) k_conv2(const typename AI::S* __restrict_
     // multiplied.  With a single chunk the weights stay in LDS for all tiles.
     int tile = blockIdx.x, ch = 0;
     if (tile >= ntiles) return;
-    load(tile, 0, true);
+    TileXY cur{tile % gx, (tile / gx) % gy, tile / (gx * gy)};
+    load(cur, 0, true);
     f32x4 acc[MT][NT];
     for (bool first = true;; first = false) {
         if (ch == 0) {
@@ -204,12 +231,14 @@ __global__ void __launch_bounds__(256) k_conv2(const typename AI::S* __restrict_
         store(nch > 1 || first);
         __syncthreads();
         int ntile = tile, nc = ch + 1;
+        TileXY nxt = cur;
         if (nc == nch) {
             nc = 0;
-            ntile += gridDim.x;
+            ntile += G;
+            nxt = next_tile(cur);
         }
         const bool more = ntile < ntiles;
-        if (more) load(ntile, nc * kKc, nch > 1);
+        if (more) load(nxt, nc * kKc, nch > 1);
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap % 3;
@@ -226,32 +255,32 @@ __global__ void __launch_bounds__(256) k_conv2(const typename AI::S* __restrict_
                 for (int m = 0; m < MT; ++m) acc[m][j] = mfma32(a[m], bw[j], acc[m][j]);
         }
         if (ch == nch - 1) {
-            const int xt = tile % gx, r = tile / gx;
-            const int yt = r % gy, b = r / gy;
-            const int y = yt * kRows + wave;
+            const int y = cur.y * kRows + wave;
             if (y < H) {
+                const int px0 = cur.x * T::TW + 4 * (lane >> 4);
+                const int row = ((cur.b * H + y) * W + px0) * Cout + n0 + (lane & 15);
 #pragma unroll
                 for (int j = 0; j < NT; ++j) {
-                    const int co = n0 + 16 * j + (lane & 15);
-                    const float bc = bias ? bias[co] : 0.f;
+                    const float bc = bias ? bias[n0 + 16 * j + (lane & 15)] : 0.f;
 #pragma unroll
                     for (int m = 0; m < MT; ++m) {
 #pragma unroll
                         for (int t = 0; t < 4; ++t) {
-                            const int px = xt * T::TW + 16 * m + 4 * (lane >> 4) + t;
                             float v = acc[m][j][t] + bc;
                             v = (act && v < 0.f) ? slope * v : v;
-                            if (px < W) {
+                            if (px0 + 16 * m + t < W) {
+                                const int o = row + (16 * m + t) * Cout + 16 * j;
                                 if constexpr (kOutBf16)
-                                    out[(((long long)b * H + y) * W + px) * Cout + co] = bf16_bits(v);
+                                    out[o] = bf16_bits(v);
                                 else
-                                    out[(((long long)b * H + y) * W + px) * Cout + co] = v;
+                                    out[o] = v;
                             }
                         }
                     }
                 }
             }
         }
+        cur = nxt;
         if (!more) break;
         tile = ntile;
         ch = nc;
@@ -797,9 +826,10 @@ int eelbm_cno_conv_fwd_cat_dt(const void* src0, int32_t C0, int32_t up0, const v
         return EELBM_E_PARAM;
     if (up0 && (H % 2 != 0 || W % 2 != 0)) return EELBM_E_PARAM;
     const int Cin = C0 + C1;
-    // workgroups of 256 threads along x: their threads must number < 2^32
+    // workgroups of 256 threads along x: their threads must number < 2^32;
+    // element offsets of the tensors and of the weight copy fit in 32 bits
     if ((long long)B * ((H + kRows - 1) / kRows) * ((W + 15) / 16) >= (1ll << 24) ||
-        (long long)Cout * 9 * Cin >= (1ll << 31))
+        (long long)Cout * 9 * Cin >= (1ll << 31) || (long long)B * H * W * std::max(Cin, Cout) >= (1ll << 31))
         return EELBM_E_PARAM;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const unsigned short* w = reinterpret_cast<const unsigned short*>(wf);
