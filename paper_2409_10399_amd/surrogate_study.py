@@ -261,16 +261,22 @@ def _check_rc(rc):
     _check(rc)
 
 
-def rollout(net, lats, inst, cond, norm, t0, jumps, jump, defect_max, check_every, log, project=False):
+def rollout(net, lats, inst, cond, norm, t0, jumps, jump, defect_max, check_every, log, project=False,
+            one_batch=False):
     """Surrogate rollout of all lattices together from their LBM state at t0,
     deciding on the host after every jump (it waits for the defects) and
-    advancing only the re-anchored lattices, in a batch built for them
-    (project: each predicted jump is made to keep the gas-volume budget,
-    `conserve`, before its defect is judged).  rollout_device gives the
-    same fields without waiting for the device; on the MI355X it is the
-    slower of the two (the host issues the steps of all lattices and the
-    gated rebuilds and reads of every lattice, and its launches, not the
-    device, set the pace), so the study times this one."""
+    advancing only the re-anchored lattices (project: each predicted jump is
+    made to keep the gas-volume budget, `conserve`, before its defect is
+    judged).  Default: a batch of the re-anchored lattices built anew each
+    jump (one launch per step); one_batch: one batch of all lattices,
+    captured once into a HIP graph of `jump` steps, in which the re-anchored
+    lattices are flagged active for each jump (eelbm_batch_set_active) --
+    the same fields and, measured on the 8 test channels, the same time
+    (157 against 158 ms), so the simpler path is the default.
+    rollout_device gives the same fields without waiting for the device; on
+    the MI355X it is slower (the host issues the rebuilds and reads of every
+    lattice, and its launches, not the device, set the pace), so the study
+    times this one."""
     import torch
     from paper_2409_10399_amd import Batch
     from paper_2409_10399_amd.surrogate import apply_output, pack_input
@@ -284,6 +290,11 @@ def rollout(net, lats, inst, cond, norm, t0, jumps, jump, defect_max, check_ever
     anchors = 0
     valid = np.ones(N, dtype=bool)  # lattice i's LBM state equals f[i] at time t
     defects = []
+    if one_batch:
+        batch = Batch(lats, tile=(64, 4), graph_steps=jump)
+        flags = torch.zeros(N, dtype=torch.int32, device="cuda")
+        host_flags = torch.zeros(N, dtype=torch.int32, pin_memory=True)
+        batch.set_active(flags)
     for j in range(jumps):
         x = pack_input(f, norm.mean, norm.inv, cond, net.cin)
         pred = apply_output(f, net.infer(x), norm.dscale)
@@ -298,17 +309,26 @@ def rollout(net, lats, inst, cond, norm, t0, jumps, jump, defect_max, check_ever
                 fi = f[i].double()
                 lats[i].reinit_fields_device(t, {"alpha_g": fi[0].contiguous(), "u_g": fi[1:3].contiguous(),
                                                  "u_l": fi[3:5].contiguous(), "dp_k": fi[5].contiguous()})
-        if len(bad):
+        if one_batch:
+            # the lattices left out keep their stale state (not valid after
+            # this jump) while their time moves with the batch
+            host_flags.zero_()
+            host_flags[torch.as_tensor(bad, dtype=torch.long)] = 1
+            flags.copy_(host_flags, non_blocking=True)
+            batch.advance(jump)
+        elif len(bad):
             # the re-anchored lattices advance together, one launch per step
             Batch([lats[i] for i in bad], tile=(64, 4)).advance(jump)
-            for i in bad:
-                read_fields(lats[i], pred[i])
-            anchors += len(bad)
+        for i in bad:
+            read_fields(lats[i], pred[i])
+        anchors += len(bad)
         valid[:] = False
         valid[bad] = True
         f = pred
         t += jump
     torch.cuda.synchronize()
+    if one_batch:
+        del batch
     return f, anchors, defects
 
 

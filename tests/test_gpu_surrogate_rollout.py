@@ -46,16 +46,20 @@ def test_surrogate_rollout_beats_frozen_fields(tmp_path):
     assert np.isfinite(err)
     assert r["rel_l2_alpha_mean"] < np.mean(ts.rel_alpha(ts.start))
     # the rollout decided on the device gives the fields of the one decided
-    # on the host (which waits for the defects and batches the re-anchored
-    # lattices anew each jump), bit for bit, under policies that re-anchor
-    # some lattices and keep others
+    # on the host (which waits for the defects), and the host-decided one
+    # gives the same with one flagged batch of all lattices as with a batch
+    # of the re-anchored lattices built anew each jump -- bit for bit, under
+    # policies that re-anchor some lattices and keep others
     for dmax, chk in ((1e-3, 3), (3e-4, 0)):
         ts.restore()
         fh, ah, _ = st.rollout(net, ts.lats, ts.inst, ts.cond, norm, ts.t0, ts.jumps, ts.jump, dmax, chk, log)
         ts.restore()
+        fs, as_, _ = st.rollout(net, ts.lats, ts.inst, ts.cond, norm, ts.t0, ts.jumps, ts.jump, dmax, chk, log,
+                                one_batch=False)
+        ts.restore()
         fd, ad, _ = st.rollout_device(net, ts.lats, ts.inst, ts.cond, norm, ts.t0, ts.jumps, ts.jump, dmax, chk, log)
         print(f"  policy {dmax}:{chk}: re-anchored {ad} of {ts.jumps * 4}", flush=True)
-        assert ah == ad and torch.equal(fh, fd), (dmax, chk)
+        assert ah == ad == as_ and torch.equal(fh, fd) and torch.equal(fh, fs), (dmax, chk)
     # re-anchoring every jump reproduces plain LBM up to the rebuilds from
     # the equilibria of the fields
     r1 = ts.judge(net, norm, 1.5e-2, 1, log)
