@@ -61,8 +61,10 @@ int env_int(const char* name, int dflt) {
 // node of the tile and its one-node halo, in three planes in D3Q19; the
 // window must fit the 64 KiB a workgroup can address.
 constexpr size_t kMaxWindowBytes = 65536;
+// FP64 arithmetic and records (FP64 storage, or FP32 populations with FP64 arithmetic)
+bool f64_compute(const eelbm_params& p) { return p.storage == EELBM_FP64 || p.storage == EELBM_FP32_F64; }
 size_t window_bytes(const eelbm_params& p, int bx, int by) {
-    if (p.storage == EELBM_FP64) return 0;
+    if (f64_compute(p)) return 0;
     return (size_t)(bx + 2) * (by + 2) * (p.lattice == EELBM_D3Q19 ? 3 : 1) * 32;
 }
 bool tile_ok(const eelbm_params& p, int bx, int by) {
@@ -106,7 +108,7 @@ int validate(const eelbm_params* pp, Geometry* g) {
     const eelbm_params& p = *pp;
     if (p.abi_version != EELBM_ABI_VERSION) return fail(EELBM_E_PARAM, "abi_version mismatch");
     if (p.lattice != EELBM_D2Q9 && p.lattice != EELBM_D3Q19) return fail(EELBM_E_PARAM, "lattice must be D2Q9 or D3Q19");
-    if (p.storage < EELBM_FP64 || p.storage > EELBM_BF16) return fail(EELBM_E_PARAM, "unknown storage");
+    if (p.storage < EELBM_FP64 || p.storage > EELBM_FP32_F64) return fail(EELBM_E_PARAM, "unknown storage");
     const int D = p.lattice == EELBM_D2Q9 ? 2 : 3;
     if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(EELBM_E_PARAM, "grid sizes must be >= 1");
     if (D == 2 && p.nz != 1) return fail(EELBM_E_PARAM, "D2Q9 needs nz = 1");
@@ -114,11 +116,12 @@ int validate(const eelbm_params* pp, Geometry* g) {
     const long long n = (long long)p.nx * p.ny * p.nz;
     // every per-node array (the widest: 8-wide FP64 records) stays below 4 GiB,
     // so kernels address it with 32-bit byte offsets
-    if ((unsigned long long)n * 8 * (p.storage == EELBM_FP64 ? 8 : 4) >= (1ull << 32))
+    if ((unsigned long long)n * 8 * (f64_compute(p) ? 8 : 4) >= (1ull << 32))
         return fail(EELBM_E_PARAM, "too many nodes for one lattice");
     // ... and so does one z-plane of a population copy (buffer descriptors)
     {
-        const unsigned long long tsz = p.storage == EELBM_FP64 ? 8 : (p.storage == EELBM_FP32 ? 4 : 2);
+        const unsigned long long tsz =
+            p.storage == EELBM_FP64 ? 8 : (p.storage == EELBM_FP32 || p.storage == EELBM_FP32_F64 ? 4 : 2);
         const unsigned long long plane = (unsigned long long)p.ny * ((p.nx + 63) / 64) * 64 * 4 * (D == 2 ? 9 : 19);
         if (plane * tsz >= (1ull << 32)) return fail(EELBM_E_PARAM, "lattice plane too large");
     }
@@ -163,8 +166,8 @@ int validate(const eelbm_params* pp, Geometry* g) {
         g->n = n;
         g->flow_axis = flow_axis;
         g->face_n = flow_axis < 0 ? 0 : n / nn[flow_axis];
-        g->tsize = p.storage == EELBM_FP64 ? 8 : (p.storage == EELBM_FP32 ? 4 : 2);
-        g->csize = p.storage == EELBM_FP64 ? 8 : 4;
+        g->tsize = p.storage == EELBM_FP64 ? 8 : (p.storage == EELBM_FP32 || p.storage == EELBM_FP32_F64 ? 4 : 2);
+        g->csize = f64_compute(p) ? 8 : 4;
         set_tiles(p, g, 0, 0, -1);
         g->channel = false;
         for (int f = 0; f < 2 * D; ++f) g->channel = g->channel || p.bc[f] != EELBM_BC_PERIODIC;
@@ -483,7 +486,7 @@ int init_impl(eelbm_handle* h, int64_t t, const double* alpha_g, const double* u
         am = sum / (double)n;
     }
     if (!std::isfinite(am)) return fail(EELBM_E_NONFINITE, "non-finite initial gas fraction");
-    if (!keep) h->alpha_ref = p.storage == EELBM_FP64 ? am : (double)(float)am;
+    if (!keep) h->alpha_ref = f64_compute(p) ? am : (double)(float)am;
     if (keep) {
         // buoyancy reference of the run
     } else if (p.rho_ref_mode == EELBM_RHOREF_LIQUID) {
@@ -821,6 +824,7 @@ int check_members(eelbm_handle* const* m, int32_t n, int32_t tx, int32_t ty) {
         if (!h->initialized) return fail(EELBM_E_STATE, "batch member not initialised");
         if (h->p.lattice != m[0]->p.lattice || h->p.storage != m[0]->p.storage || h->g.channel != m[0]->g.channel)
             return fail(EELBM_E_PARAM, "batch members must share lattice, storage and boundary kind");
+        if (h->p.storage == EELBM_FP32_F64) return fail(EELBM_E_PARAM, "EELBM_FP32_F64 lattices are not batched");
         if (h->device != m[0]->device) return fail(EELBM_E_PARAM, "batch members must live on one device");
         if (h->t != m[0]->t) return fail(EELBM_E_STATE, "batch members must be at the same time step");
         if (h->cur != (int)(h->t & 1)) return fail(EELBM_E_STATE, "internal: copy parity differs from time parity");

@@ -62,6 +62,15 @@ template <>
 struct Compute<double> {
     using C = double;
 };
+// FP32 populations with FP64 arithmetic and records (EELBM_FP32_F64): the
+// storage of FP32 at the arithmetic precision of the FP64 step
+struct F32D {
+    float v;
+};
+template <>
+struct Compute<F32D> {
+    using C = double;
+};
 
 // Per-node record of 8 compute-type values written by every step (two
 // 16-byte vectors in FP32): alpha_g - a_r (renormalised alpha_g as a
@@ -239,6 +248,23 @@ struct Pop4<float> {
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const float* v,
                                               const KParams&, bool) {
         const f32x4 w = {v[0], v[1], v[2], v[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, w), r, (int)vo, (int)so, POL);
+    }
+};
+template <>
+struct Pop4<F32D> {
+    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, double* o,
+                                              const KParams&, bool) {
+        const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, kNT));
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+    template <int POL>
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const double* v,
+                                              const KParams&, bool) {
+        const f32x4 w = {(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, w), r, (int)vo, (int)so, POL);
     }
 };
@@ -1516,6 +1542,7 @@ static hipError_t go1(int storage, int bc, bool init, const KParams& p, const KB
     switch (storage) {
         case EELBM_FP64: return go2<L, double>(bc, init, p, b, c, g, bl, s);
         case EELBM_FP32: return go2<L, float>(bc, init, p, b, c, g, bl, s);
+        case EELBM_FP32_F64: return go2<L, F32D>(bc, init, p, b, c, g, bl, s);
         case EELBM_FP16: return go2<L, __half>(bc, init, p, b, c, g, bl, s);
         case EELBM_BF16: return go2<L, __hip_bfloat16>(bc, init, p, b, c, g, bl, s);
     }

@@ -163,6 +163,8 @@ def test_batch_member_matches_oracle():
 def test_batch_rejects_mixed_members():
     from paper_2409_10399_amd import Batch, EelbmError
     ws = members()[:2]
+    with pytest.raises(EelbmError):  # FP32 storage with FP64 arithmetic runs single lattices only
+        Batch(_lattices(ws, "fp32x"), tile=(64, 4))
     a = _lattices(ws[:1], "fp32") + _lattices(ws[1:], "fp64")
     with pytest.raises(EelbmError):
         Batch(a)

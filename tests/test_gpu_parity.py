@@ -29,10 +29,12 @@ def box_oracle():
     return cfg, f, run_oracle(cfg, f, 1000).read()
 
 
-@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp32", BOX_FP32_TOL)])
+@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp32", BOX_FP32_TOL), ("fp32x", FP32_TOL)])
 def test_periodic_box_1000_steps(box_oracle, storage, tol):
     """D2Q9 64x64 periodic box, R = 10, gas fraction 0.1 + seeded modes,
-    gravity on, Clift-Grace-Weber drag, 1000 steps."""
+    gravity on, Clift-Grace-Weber drag, 1000 steps.  fp32x (FP32 populations,
+    FP64 arithmetic) meets the common bound on every field: what the FP32
+    step misses on delta p_k is its arithmetic, not its storage."""
     cfg, f, ro = box_oracle
     g = run_gpu(cfg, f, 1000, storage)
     check(g.read_all(), ro, storage, tol, "1000 steps")
@@ -49,7 +51,7 @@ def channel_oracle():
     return cfg, f, run_oracle(cfg, f, 1000).read()
 
 
-@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL), ("fp32x", FP32_TOL)])
 def test_small_channel_1000_steps(channel_oracle, storage, tol):
     """Bubble-column channel physics (R = 1000, CGW 3 mm, dashpot + lag
     n_gamma = 200, inlet ramp and noise, walls, outlet) on a 40x48 grid."""
@@ -74,6 +76,7 @@ def test_d3q19_periodic():
     f = {k: _resize3(v, (n + 1, n + 2, n)) for k, v in f.items()}
     compare(cfg, f, 60, "fp64", FP64_TOL)
     compare(cfg, f, 60, "fp32", D3_BOX_FP32_TOL)
+    compare(cfg, f, 60, "fp32x", FP32_TOL)
 
 
 
