@@ -68,6 +68,10 @@ extern "C" {
 /* FP32 populations with the FP64 step's arithmetic and FP64 records: the
  * rounding of FP32 storage alone (single lattices; batches refuse it) */
 #define EELBM_FP32_F64 4
+/* Mixed storage: f_g in FP32, f_l, f_alpha_g, f_alpha_l in FP16 (scaled
+ * residuals as in FP16 storage), 12 bytes per direction instead of 16; FP32
+ * arithmetic (single lattices; batches refuse it) */
+#define EELBM_MIXED 5
 
 /* boundary type of one face (Sec. 3.5) */
 #define EELBM_BC_PERIODIC 0
@@ -91,7 +95,7 @@ extern "C" {
 typedef struct eelbm_params {
     int32_t abi_version;   /* must be EELBM_ABI_VERSION */
     int32_t lattice;       /* EELBM_D2Q9 or EELBM_D3Q19 */
-    int32_t storage;       /* EELBM_FP64 / FP32 / FP16 / BF16 / FP32_F64 */
+    int32_t storage;       /* EELBM_FP64 / FP32 / FP16 / BF16 / FP32_F64 / MIXED */
     int32_t nx, ny, nz;    /* nz = 1 for D2Q9 */
     int32_t bc[6];         /* faces x-, x+, y-, y+, z-, z+; periodic faces come in pairs */
     int32_t up_axis;       /* 0, 1, 2: direction of +buoyancy (and of the inlet flow) */

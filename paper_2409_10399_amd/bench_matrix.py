@@ -24,7 +24,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 def bytes_per_node(D, Q, storage, lag):
-    tb = {"fp64": 8, "fp32": 4, "fp32x": 4, "fp16": 2, "bf16": 2}[storage]
+    tb = {"fp64": 8, "fp32": 4, "fp32x": 4, "mixed": 3, "fp16": 2, "bf16": 2}[storage]
     cb = 8 if storage in ("fp64", "fp32x") else 4  # fp32x: FP32 populations, FP64 records
     return 2 * 4 * Q * tb + 2 * (1 + D) * cb + (3 * cb if lag else 0)
 

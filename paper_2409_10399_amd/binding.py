@@ -17,7 +17,8 @@ LIB_PATH = os.environ.get("EELBM_LIB") or os.path.join(_HERE, "_lib", "libeelbm.
 ABI_VERSION = 1
 E_CODES = {-1: "EELBM_E_PARAM", -2: "EELBM_E_SIZE", -3: "EELBM_E_HIP", -4: "EELBM_E_NONFINITE", -5: "EELBM_E_STATE"}
 LATTICE = {"D2Q9": 2, "D3Q19": 3}
-STORAGE = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "fp32x": 4}  # fp32x: FP32 populations, FP64 arithmetic
+# fp32x: FP32 populations, FP64 arithmetic; mixed: f_g FP32, f_l and f_alpha FP16
+STORAGE = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "fp32x": 4, "mixed": 5}
 BC = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3}
 DRAG = {"const": 0, "cgw": 1}
 FIELD = {"alpha_g": 0, "alpha_l": 1, "u_g": 2, "u_l": 3, "p_k": 4, "dp_k": 5}

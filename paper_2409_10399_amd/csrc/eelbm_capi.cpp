@@ -63,6 +63,17 @@ int env_int(const char* name, int dflt) {
 constexpr size_t kMaxWindowBytes = 65536;
 // FP64 arithmetic and records (FP64 storage, or FP32 populations with FP64 arithmetic)
 bool f64_compute(const eelbm_params& p) { return p.storage == EELBM_FP64 || p.storage == EELBM_FP32_F64; }
+// bytes per stored population value: a direction's four sets take 4x this
+// (mixed storage: 12 bytes, FP32 f_g and three FP16 values)
+size_t pop_value_bytes(const eelbm_params& p) {
+    switch (p.storage) {
+        case EELBM_FP64: return 8;
+        case EELBM_FP32:
+        case EELBM_FP32_F64: return 4;
+        case EELBM_MIXED: return 3;
+        default: return 2;
+    }
+}
 size_t window_bytes(const eelbm_params& p, int bx, int by) {
     if (f64_compute(p)) return 0;
     return (size_t)(bx + 2) * (by + 2) * (p.lattice == EELBM_D3Q19 ? 3 : 1) * 32;
@@ -108,7 +119,7 @@ int validate(const eelbm_params* pp, Geometry* g) {
     const eelbm_params& p = *pp;
     if (p.abi_version != EELBM_ABI_VERSION) return fail(EELBM_E_PARAM, "abi_version mismatch");
     if (p.lattice != EELBM_D2Q9 && p.lattice != EELBM_D3Q19) return fail(EELBM_E_PARAM, "lattice must be D2Q9 or D3Q19");
-    if (p.storage < EELBM_FP64 || p.storage > EELBM_FP32_F64) return fail(EELBM_E_PARAM, "unknown storage");
+    if (p.storage < EELBM_FP64 || p.storage > EELBM_MIXED) return fail(EELBM_E_PARAM, "unknown storage");
     const int D = p.lattice == EELBM_D2Q9 ? 2 : 3;
     if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(EELBM_E_PARAM, "grid sizes must be >= 1");
     if (D == 2 && p.nz != 1) return fail(EELBM_E_PARAM, "D2Q9 needs nz = 1");
@@ -120,8 +131,7 @@ int validate(const eelbm_params* pp, Geometry* g) {
         return fail(EELBM_E_PARAM, "too many nodes for one lattice");
     // ... and so does one z-plane of a population copy (buffer descriptors)
     {
-        const unsigned long long tsz =
-            p.storage == EELBM_FP64 ? 8 : (p.storage == EELBM_FP32 || p.storage == EELBM_FP32_F64 ? 4 : 2);
+        const unsigned long long tsz = pop_value_bytes(p);
         const unsigned long long plane = (unsigned long long)p.ny * ((p.nx + 63) / 64) * 64 * 4 * (D == 2 ? 9 : 19);
         if (plane * tsz >= (1ull << 32)) return fail(EELBM_E_PARAM, "lattice plane too large");
     }
@@ -166,7 +176,7 @@ int validate(const eelbm_params* pp, Geometry* g) {
         g->n = n;
         g->flow_axis = flow_axis;
         g->face_n = flow_axis < 0 ? 0 : n / nn[flow_axis];
-        g->tsize = p.storage == EELBM_FP64 ? 8 : (p.storage == EELBM_FP32 || p.storage == EELBM_FP32_F64 ? 4 : 2);
+        g->tsize = pop_value_bytes(p);
         g->csize = f64_compute(p) ? 8 : 4;
         set_tiles(p, g, 0, 0, -1);
         g->channel = false;
@@ -329,7 +339,7 @@ void fill_kparams(eelbm_handle* h) {
     k.ul_in_min = p.ul_in_min;
     k.n_ramp = p.n_ramp;
     k.alpha_ref = h->alpha_ref;
-    // FP16 scales of the stored residuals (only used with FP16 storage): 2^20
+    // FP16 scales of the stored residuals (FP16 and mixed storage): 2^20
     // for f_g, f_ag, f_al, 2^20 * 2^round(log2 min(R, 64)) for the moving
     // populations of f_l (its rest population is stored unscaled)
     const double R = p.rho_l / p.rho_g;
@@ -824,7 +834,8 @@ int check_members(eelbm_handle* const* m, int32_t n, int32_t tx, int32_t ty) {
         if (!h->initialized) return fail(EELBM_E_STATE, "batch member not initialised");
         if (h->p.lattice != m[0]->p.lattice || h->p.storage != m[0]->p.storage || h->g.channel != m[0]->g.channel)
             return fail(EELBM_E_PARAM, "batch members must share lattice, storage and boundary kind");
-        if (h->p.storage == EELBM_FP32_F64) return fail(EELBM_E_PARAM, "EELBM_FP32_F64 lattices are not batched");
+        if (h->p.storage == EELBM_FP32_F64 || h->p.storage == EELBM_MIXED)
+            return fail(EELBM_E_PARAM, "EELBM_FP32_F64 and EELBM_MIXED lattices are not batched");
         if (h->device != m[0]->device) return fail(EELBM_E_PARAM, "batch members must live on one device");
         if (h->t != m[0]->t) return fail(EELBM_E_STATE, "batch members must be at the same time step");
         if (h->cur != (int)(h->t & 1)) return fail(EELBM_E_STATE, "internal: copy parity differs from time parity");

@@ -42,6 +42,7 @@ namespace eelbm {
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -334,6 +335,40 @@ struct Pop4Half {
 };
 template <>
 struct Pop4<__half> : Pop4Half<__half> {};
+// Mixed storage (EELBM_MIXED): f_g in FP32, f_l, f_ag, f_al in FP16 with
+// the scales above, one 12-byte group per direction (the tag type is 3
+// bytes, a quarter of the group).  The gas density, which carries the
+// pressure delta p_k, keeps the resolution of FP32 storage; the liquid and
+// volume-fraction populations take 16 bits.
+struct Mix12 {
+    unsigned char b[3];
+};
+template <>
+struct Pop4<Mix12> {
+    static __device__ __forceinline__ float h2f(unsigned short h, float down) {
+        return __half2float(__ushort_as_half(h)) * down;
+    }
+    static __device__ __forceinline__ unsigned short f2h(float v, float up) {
+        return __half_as_ushort(__float2half_rn(v * up));
+    }
+    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float* o,
+                                              const KParams& p, bool rest) {
+        const u32x3 v = __builtin_bit_cast(u32x3, __builtin_amdgcn_raw_buffer_load_b96(r, (int)vo, (int)so, kNT));
+        o[0] = __builtin_bit_cast(float, v.x);
+        o[1] = h2f((unsigned short)(v.y & 0xffffu), rest ? 1.0f : p.h16_down[1]);
+        o[2] = h2f((unsigned short)(v.y >> 16), p.h16_down[0]);
+        o[3] = h2f((unsigned short)(v.z & 0xffffu), p.h16_down[0]);
+    }
+    template <int POL>
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, const float* v,
+                                              const KParams& p, bool rest) {
+        u32x3 w;
+        w.x = __builtin_bit_cast(unsigned, v[0]);
+        w.y = (unsigned)f2h(v[1], rest ? 1.0f : p.h16_up[1]) | ((unsigned)f2h(v[2], p.h16_up[0]) << 16);
+        w.z = (unsigned)f2h(v[3], p.h16_up[0]);
+        __builtin_amdgcn_raw_buffer_store_b96(w, r, (int)vo, (int)so, POL);
+    }
+};
 template <>
 struct Pop4<__hip_bfloat16> : Pop4Half<__hip_bfloat16> {};
 
@@ -1543,6 +1578,7 @@ static hipError_t go1(int storage, int bc, bool init, const KParams& p, const KB
         case EELBM_FP64: return go2<L, double>(bc, init, p, b, c, g, bl, s);
         case EELBM_FP32: return go2<L, float>(bc, init, p, b, c, g, bl, s);
         case EELBM_FP32_F64: return go2<L, F32D>(bc, init, p, b, c, g, bl, s);
+        case EELBM_MIXED: return go2<L, Mix12>(bc, init, p, b, c, g, bl, s);
         case EELBM_FP16: return go2<L, __half>(bc, init, p, b, c, g, bl, s);
         case EELBM_BF16: return go2<L, __hip_bfloat16>(bc, init, p, b, c, g, bl, s);
     }

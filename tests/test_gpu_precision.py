@@ -11,8 +11,11 @@ about 3, and are the stated precision of each storage type:
   R >= 64), relative resolution 2^-11; BF16 holds them unscaled, 2^-8;
 * delta p_k of a column at rest (~1e-4 of the non-equilibrium part of the
   residuals) is below the resolution of both 16-bit types: its bounds are
-  stated, not tight -- FP32 storage is the choice where the pressure field
-  of such a column matters.
+  stated, not tight;
+* mixed storage (f_g in FP32, f_l, f_alpha in FP16: 12 bytes per direction
+  against 16) keeps delta p_k and u_g at FP32 level with the liquid and
+  volume fractions at FP16 level -- the choice where the pressure of such a
+  column matters and the bytes of FP32 do not.
 """
 import numpy as np
 import pytest
@@ -27,11 +30,13 @@ CHANNEL = {  # D2Q9 40x48 and 320x40 channels, R = 1000, CGW, dashpot + lag, 100
     "fp32": {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5, "dp_k": 1e-5},
     "fp16": {"alpha_g": 2e-5, "u_g": 5e-4, "u_l": 7e-4, "dp_k": 8e-4},
     "bf16": {"alpha_g": 5e-4, "u_g": 1.5e-2, "u_l": 3.5e-2, "dp_k": 3e-2},
+    "mixed": {"alpha_g": 1e-5, "u_g": 1.5e-5, "u_l": 3e-4, "dp_k": 3e-5},
 }
 COLUMN = {  # D3Q19 32^3 periodic column, R = 1000, blobs on alpha 0.01, 200 steps
     "fp32": {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5, "dp_k": 1e-5},
     "fp16": {"alpha_g": 1e-5, "u_g": 6e-5, "u_l": 1e-4, "dp_k": 0.7},
     "bf16": {"alpha_g": 5e-5, "u_g": 7e-4, "u_l": 2e-3, "dp_k": 9.0},
+    "mixed": {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-4, "dp_k": 1.5e-5},
 }
 
 
@@ -62,6 +67,7 @@ CROP64 = {  # 64^3 crop of the 256^3 column workload (256 blobs), 20 steps
     "fp32": {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 1e-5, "dp_k": 3e-3},
     "fp16": {"alpha_g": 1e-5, "u_g": 7e-4, "u_l": 1e-3, "dp_k": 15.0},
     "bf16": {"alpha_g": 6e-5, "u_g": 3e-3, "u_l": 2.5e-3, "dp_k": 20.0},
+    "mixed": {"alpha_g": 1e-5, "u_g": 1e-5, "u_l": 5e-4, "dp_k": 3e-3},
 }
 
 
@@ -84,6 +90,6 @@ def test_storage_precision_column_crop64():
         print(f"  {storage} " + " ".join(f"{k}={errs[k]:.2e}" for k in FIELDS), flush=True)
         for k in FIELDS:
             assert np.isfinite(errs[k]) and errs[k] <= tol[k], (storage, k, errs[k], tol[k])
-    for storage in ("fp16", "bf16"):
+    for storage in ("fp16", "bf16", "mixed"):
         print(f"  {storage} vs fp32 storage " + " ".join(f"{k}={rel_l2(g[storage][k], g['fp32'][k]):.2e}" for k in FIELDS),
               flush=True)
