@@ -94,15 +94,25 @@ def cpu_baseline(steps=20, procs=None):
         span = max(d["t1"] for d in out) - min(d["t0"] for d in out)
         return sum(d["nodes"] for d in out) * steps / span / 1e6, span
 
+    # the FP64 periodic-box case (D2Q9 64x64, R = 10) on one core, for scale
+    box = code.replace("workloads.channel_2d()", "workloads.periodic_box_2d()").replace(
+        "o.step(%d)" % steps, "o.step(200)").replace("* steps", "* 200")
     try:
         one, dt1 = run(1)
         allc, dtn = run(procs)
+        pb = subprocess.run([sys.executable, "-c", box], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                            env=env, timeout=600)
+        if pb.returncode != 0:
+            raise RuntimeError(pb.stderr[-400:])
+        b = json.loads(pb.stdout.strip().splitlines()[-1])
+        box_mlups = b["nodes"] * 200 / (b["t1"] - b["t0"]) / 1e6
     except (RuntimeError, subprocess.TimeoutExpired) as e:
         return {"error": str(e)[-400:]}
     return {"value": allc, "unit": "MLUPS", "cores": procs, "kind": "oracle",
             "sample": f"D2Q9 1024x1024 channel, {steps} steps per copy, NumPy FP64, {procs} single-thread "
                       f"copies at once ({dtn:.1f} s span); one copy alone: {one:.3f} MLUPS ({dt1:.1f} s)",
-            "single_core": one, "host_cpus": ncpu, "cpu_model": model}
+            "single_core": one, "host_cpus": ncpu, "cpu_model": model,
+            "periodic_box_64_single_core": box_mlups}
 
 
 def surrogate_leg():
