@@ -68,3 +68,36 @@ def test_map_physical_reproduces_test4_numbers():
     assert abs(m["c"] / pr["c"] - 1) < 1e-3
     with pytest.raises(b.EelbmError):
         b.map_physical(-1.0, 1.0, 1.0, 1.0)
+
+
+def test_storage_sizes_of_every_mode():
+    """State bytes follow the bytes per stored population value: FP64 8,
+    FP32 and FP32-with-FP64-arithmetic 4 (the latter with FP64 records),
+    mixed 3 (a 12-byte group per direction), FP16/BF16 2."""
+    b = _lib()
+    cfg, _ = workloads.channel_2d(nx=128, ny=64)
+    sizes = {s: b.state_bytes(cfg, s) for s in ("fp64", "fp32", "fp32x", "mixed", "fp16", "bf16")}
+    assert sizes["fp16"] == sizes["bf16"] < sizes["mixed"] < sizes["fp32"] < sizes["fp32x"] < sizes["fp64"]
+    n = 128 * 64
+    # population copies differ by 2 x 4 x 9 values x the byte difference per value
+    assert sizes["fp32"] - sizes["mixed"] == 2 * 4 * 9 * n * (4 - 3)
+    assert sizes["mixed"] - sizes["fp16"] == 2 * 4 * 9 * n * (3 - 2)
+
+
+def test_new_entry_points_validate_without_a_gpu():
+    """Parameter checks that return before any device work."""
+    b = _lib()
+    L = b.lib()
+    assert L.eelbm_cno_conv_set_tile(3, 1) != 0 and L.eelbm_cno_conv_set_tile(1, 5) != 0
+    assert L.eelbm_cno_conv_set_tile(0, 0) == 0
+    assert L.eelbm_batch_set_active(None, None) != 0
+    assert L.eelbm_batch_rebuild_gated(None, 0, None, None) != 0
+    assert L.eelbm_batch_read_fields(None, None) != 0
+    assert L.eelbm_cno_reanchor_policy(None, 1, 1e-3, 0, None, None, None, None, None) != 0
+    assert L.eelbm_cno_select(None, 1, 1, None, None, None, None) != 0
+    assert L.eelbm_cno_volume_defect(None, None, 1, 3, 1, 1, None, None, None) != 0
+    assert L.eelbm_cno_pool_bf16(None, 1, 2, 2, 16, None, None) != 0
+    # a shape whose tensors hold 2^31 values or more is refused before launch
+    big = ctypes.c_void_p(16)
+    assert L.eelbm_cno_conv_fwd_cat_dt(big, 64, 0, None, 0, 16, 2048, 2048, big, None, 64, big, 0, 0.1, 0, 0,
+                                       None) != 0
