@@ -37,9 +37,11 @@ def algorithmic_bytes_per_node(D, Q, tbytes, cbytes, lag):
     2Q source-scheme populations read and written, and the 3 lag values
     (S''_g, S''_l, Lambda') read; their write every n_gamma steps is not
     counted.  D2Q9 FP32: 288 + 24 + 12 = 324 B.  The kernel moves more than
-    this minimum: its record also carries u_g, u_l and eps_g - 1 as the
-    reference of the stored residuals (D2Q9 FP32: 360 B per node-update);
-    that overhead of the storage format counts against the kernel."""
+    this minimum: its record (alpha_g, u_g, u_l, eps_g - 1: 2 + 2D values)
+    also carries u_g, u_l and eps_g - 1 as the reference of the stored
+    residuals (D2Q9 FP32: 348 B per node-update, 24 B records read and
+    written); that overhead of the storage format counts against the
+    kernel."""
     return 2 * 4 * Q * tbytes + 2 * (1 + D) * cbytes + (3 * cbytes if lag else 0)
 
 

@@ -206,15 +206,16 @@ size_t pop_bytes(const eelbm_params& p, const Geometry& g) { return (size_t)p.nz
 // found there in the next when one set of them is smaller
 constexpr size_t kLastLevelCacheBytes = 256ull << 20;
 
-// imposed-velocity region of one ping-pong copy: [n] 4-wide records, then
-// [n] alpha_l values (used only without renormalisation)
-size_t cf_records_bytes(const Geometry& g) { return align256(8 * (size_t)g.n * g.csize); }
+// imposed-velocity region of one ping-pong copy: [n] records of 2 + 2D
+// values (8 in D3Q19, 6 in D2Q9), then [n] alpha_l values (used only without
+// renormalisation)
+size_t cf_records_bytes(const Geometry& g) { return align256((g.D == 3 ? 8 : 6) * (size_t)g.n * g.csize); }
 size_t cf_region_bytes(const Geometry& g) { return cf_records_bytes(g) + (size_t)g.n * g.csize; }
-// lag region: [n] 2-wide records (S''_g, S''_l), then [n] Lambda' in 3D
+// lag region: [n] 2-wide records (S''_g, S''_l), then [n] Lambda'
 size_t lag_records_bytes(const Geometry& g) { return align256(2 * (size_t)g.n * g.csize); }
 size_t lag_region_bytes(const eelbm_params& p, const Geometry& g) {
     if (p.n_gamma <= 1) return 0;
-    return lag_records_bytes(g) + (g.D == 3 ? (size_t)g.n * g.csize : 0);
+    return lag_records_bytes(g) + (size_t)g.n * g.csize;
 }
 
 Layout layout(const eelbm_params& p, const Geometry& g) {

@@ -73,12 +73,12 @@ struct Compute<F32D> {
     using C = double;
 };
 
-// Per-node record of 8 compute-type values written by every step (two
-// 16-byte vectors in FP32): alpha_g - a_r (renormalised alpha_g as a
-// deviation from the reference gas fraction a_r, so that carrying it from step
-// to step rounds at the scale of the deviation), u_g, u_l and the gas
-// density deviation eps_g - 1 of the node's collision, plus Lambda' (the
-// lagged Clift-Grace-Weber factor) in D2Q9.  It serves two purposes:
+// Per-node record of 2 + 2D compute-type values written by every step (8 in
+// D3Q19: two 16-byte vectors in FP32; 6 in D2Q9: 24 bytes in FP32, 48 in
+// FP64): alpha_g - a_r (renormalised alpha_g as a deviation from the
+// reference gas fraction a_r, so that carrying it from step to step rounds at
+// the scale of the deviation), u_g, u_l and the gas density deviation
+// eps_g - 1 of the node's collision.  It serves two purposes:
 //  * the post-collision f_b of the lattice kinetic scheme is the pure
 //    function f^eq(1, c_phi) of alpha_g and u_g - u_l (Eqs. (95), (97) with
 //    beta = 1), so f_b is rebuilt at the gather from the upstream record
@@ -95,7 +95,9 @@ struct Compute<F32D> {
 //    record back; any rounding of the record is the same on both sides.
 template <int D>
 constexpr int kDe = 1 + 2 * D;  // slot of eps_g - 1
-constexpr int kLam = 6;         // slot of Lambda' (D2Q9; read by the node itself only)
+// bytes of one record in the record array (the stride between nodes)
+template <int D, class C>
+constexpr unsigned kRecBytes = (unsigned)((D == 3 ? 8 : 6) * sizeof(C));
 template <class C>
 struct alignas(8 * sizeof(C)) Rec8 {
     C v[8];
@@ -123,8 +125,9 @@ __device__ __forceinline__ Rec8<double> ld_rec8(__amdgpu_buffer_rsrc_t r, unsign
     t.d = __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)(so + 48), 0);
     return __builtin_bit_cast(Rec8<double>, t);
 }
-// the part of an upstream node's record the gather uses: all 8 slots in
-// D3Q19, slots 0-5 in D2Q9 (one 16-byte and one 8-byte load in FP32)
+// one node's record: all 8 slots in D3Q19, slots 0-5 in D2Q9 (one 16-byte
+// and one 8-byte load in FP32; the 24-byte stride leaves every second record
+// 8-byte aligned, which buffer loads of several dwords accept)
 template <int D>
 __device__ __forceinline__ Rec8<float> ld_rec_up(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, float c) {
     if constexpr (D == 3) {
@@ -162,15 +165,23 @@ __device__ __forceinline__ Rec8<double> ld_rec_up(__amdgpu_buffer_rsrc_t r, unsi
         return o;
     }
 }
-__device__ __forceinline__ void st_rec8(__amdgpu_buffer_rsrc_t r, unsigned vo, const Rec8<float>& v) {
+// stores the slots ld_rec_up reads (kRecBytes<D, C> bytes at vo)
+template <int D>
+__device__ __forceinline__ void st_rec(__amdgpu_buffer_rsrc_t r, unsigned vo, const Rec8<float>& v) {
     struct Two {
         u32x4 a, b;
     };
     const Two t = __builtin_bit_cast(Two, v);
     __builtin_amdgcn_raw_buffer_store_b128(t.a, r, (int)vo, 0, 0);
-    __builtin_amdgcn_raw_buffer_store_b128(t.b, r, (int)vo, 16, 0);
+    if constexpr (D == 3) {
+        __builtin_amdgcn_raw_buffer_store_b128(t.b, r, (int)vo, 16, 0);
+    } else {
+        const u32x2 lo = {t.b.x, t.b.y};
+        __builtin_amdgcn_raw_buffer_store_b64(lo, r, (int)vo, 16, 0);
+    }
 }
-__device__ __forceinline__ void st_rec8(__amdgpu_buffer_rsrc_t r, unsigned vo, const Rec8<double>& v) {
+template <int D>
+__device__ __forceinline__ void st_rec(__amdgpu_buffer_rsrc_t r, unsigned vo, const Rec8<double>& v) {
     struct Four {
         u32x4 a, b, c, d;
     };
@@ -178,7 +189,7 @@ __device__ __forceinline__ void st_rec8(__amdgpu_buffer_rsrc_t r, unsigned vo, c
     __builtin_amdgcn_raw_buffer_store_b128(t.a, r, (int)vo, 0, 0);
     __builtin_amdgcn_raw_buffer_store_b128(t.b, r, (int)vo, 16, 0);
     __builtin_amdgcn_raw_buffer_store_b128(t.c, r, (int)vo, 32, 0);
-    __builtin_amdgcn_raw_buffer_store_b128(t.d, r, (int)vo, 48, 0);
+    if constexpr (D == 3) __builtin_amdgcn_raw_buffer_store_b128(t.d, r, (int)vo, 48, 0);
 }
 
 // Upstream records staged in LDS (FP32 compute): one 32-byte slot per node
@@ -588,12 +599,13 @@ __device__ __forceinline__ double ramp(double t, double ymax, double ymin, doubl
 }
 
 // One node update of one tile: `tile` is the tile's index over all planes,
-// `part` the slot of its diagnostic partial sums.  OUT instantiates the
-// diagnostics and field read-out (written when the step's control asks for
-// them); the steps that never write them run an instantiation without that
-// code, which needs fewer registers (D2Q9 FP32 channel: 88 instead of 99
-// VGPRs, 5 waves per SIMD instead of 4) and computes the same bits.
-template <class L, class T, int BC, bool INIT, bool OUT = true, bool NTS = false>
+// `part` the slot of its diagnostic partial sums.  Diagnostics and the field
+// read-out are written when the step's control asks for them, by the same
+// instantiation that runs the steps without them: a separate instantiation
+// without that code needs 3-4 fewer VGPRs (no change of occupancy) but, with
+// its other basic blocks, the compiler fused other multiply-add pairs, so a
+// lattice's state came to depend on the steps at which it was read.
+template <class L, class T, int BC, bool INIT, bool NTS = false>
 __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, const KCtl& ctl, long long tile,
                                           long long part) {
     using C = typename Compute<T>::C;
@@ -624,7 +636,7 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
     const bool act = x < p.nx && y < p.ny;
     const long long n = p.n;
     const long long node = ((long long)z * p.ny + y) * p.nx + x;
-    const unsigned rb = (unsigned)node * (unsigned)sizeof(Rec8<C>);   // ... in the record array
+    const unsigned rb = (unsigned)node * kRecBytes<D, C>;             // ... in the record array
     const unsigned cb = (unsigned)node * (unsigned)sizeof(C);         // ... in a scalar array
     const int co[3] = {x, y, z};
     const int nn[3] = {p.nx, p.ny, p.nz};
@@ -659,7 +671,7 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
             const int ys = wrap_axis(y0 + j, p.ny, per(1));
             const int zs = D == 3 ? wrap_axis(z - 1 + k, p.nz, per(2)) : 0;
             const long long src = ((long long)zs * p.ny + ys) * p.nx + xs;
-            lds_put<D>(lds_win + e, ld_rec_up<D>(rw, (unsigned)src * (unsigned)sizeof(Rec8<float>), 0u, 0.0f));
+            lds_put<D>(lds_win + e, ld_rec_up<D>(rw, (unsigned)src * kRecBytes<D, float>, 0u, 0.0f));
         }
         __syncthreads();
     }
@@ -780,8 +792,10 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
         Rec8<C> r0;
         if constexpr (INIT) {
             r0 = stage_rec<L, C>(b.stage, node, n, p.alpha_ref);
+        } else if constexpr (kStage) {
+            r0 = lds_get<D>(lds_win + win_at(0));  // the centre of the staged window
         } else {
-            r0 = ld_rec8(rsrc(cfin), rb, 0u, C(0));
+            r0 = ld_rec_up<D>(rsrc(cfin), rb, 0u, C(0));
         }
         const C a0d = r0.v[0], a0 = ar + a0d, de0 = r0.v[kDe<D>];
         C ug0[D], ul0[D];
@@ -790,7 +804,6 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
             ug0[a] = r0.v[1 + a];
             ul0[a] = r0.v[1 + D + a];
         }
-        const C lam_prev = D == 2 ? r0.v[kLam] : C(0);  // lagged Lambda' of the last refresh (D2Q9)
         // the node's own imposed velocities of the source schemes (Eq. (97))
         C al0 = C(1) - a0;
         if constexpr (!INIT) {
@@ -905,7 +918,7 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                     if constexpr (kStage)
                         rs = lds_get<D>(lds_win + win_at(q));
                     else
-                        rs = ld_rec_up<D>(rsrc(cfin), (unsigned)src * (unsigned)sizeof(Rec8<C>), 0u, C(0));
+                        rs = ld_rec_up<D>(rsrc(cfin), (unsigned)src * kRecBytes<D, C>, 0u, C(0));
                 }
                 const C g4[4] = {f[0][q], f[1][q], f[2][q], f[3][q]};
                 C n4[4];
@@ -992,7 +1005,7 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
             }
         }
 
-        if (OUT && ctl.write_diag) {
+        if (ctl.write_diag) {
             int bad = 0;
 #pragma unroll
             for (int s = 0; s < 4; ++s)
@@ -1119,12 +1132,12 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                 r.v[0] = Spg;
                 r.v[1] = Spl;
                 *at(lag, (unsigned)node * (unsigned)sizeof(Rec2<C>)) = r;
-                if (D == 3) *at(lagl, cb) = Lam;
+                *at(lagl, cb) = Lam;
             } else {
                 const Rec2<C> r = *at(lag, (unsigned)node * (unsigned)sizeof(Rec2<C>));
                 S2g = r.v[0];
                 S2l = r.v[1];
-                Laml = D == 3 ? *at(lagl, cb) : lam_prev;
+                Laml = *at(lagl, cb);
             }
         }
 
@@ -1276,12 +1289,8 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
                 r.v[1 + a] = ug[a];
                 r.v[1 + D + a] = ul[a];
             }
-            if (D == 2) {
-                r.v[kLam] = Laml;  // carried forward for the lagged drag
-                r.v[7] = C(0);
-            }
             r.v[kDe<D>] = deg;
-            st_rec8(rsrc(b.cf_out), rb, r);
+            st_rec<D>(rsrc(b.cf_out), rb, r);
             if (!p.renorm) *at(static_cast<C*>(b.al_out), cb) = all;
         }
 
@@ -1319,7 +1328,7 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
         }
 
         // ------------------------------------------------ output fields
-        if (OUT && ctl.write_macro) {
+        if (ctl.write_macro) {
             double* m = b.macro;
             m[node] = double(alg);
             m[n + node] = double(all);
@@ -1330,7 +1339,7 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
             }
             m[(2 + 2 * D) * n + node] = double(degA) / 3.0;
         }
-        if (OUT && ctl.write_diag) {
+        if (ctl.write_diag) {
             dsum[0] = double(ar) + double(sag);
             dsum[1] = (1.0 - double(ar)) + double(sal);
             dsum[2] = double(alg);
@@ -1348,7 +1357,7 @@ __device__ __forceinline__ void step_body(const KParams& p, const KBuffers& b, c
     }
 
     // ---------------- FP64 wavefront -> block reduction of the diagnostics
-    if (OUT && ctl.write_diag) {
+    if (ctl.write_diag) {
         __shared__ double red[kNDiag][4];
         // block sizes are whole wavefronts (checked on the host)
         const int tid = threadIdx.y * blockDim.x + threadIdx.x;
@@ -1381,13 +1390,13 @@ __device__ __forceinline__ long long xcd_tile(long long id, long long nb, int re
 }
 
 
-template <class L, class T, int BC, bool INIT, bool OUT, bool NTS>
+template <class L, class T, int BC, bool INIT, bool NTS>
 __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b, const KCtl ctl) {
     if constexpr (INIT) {
         // a gated rebuild: the whole grid skips it when the device flag is 0
         if (ctl.gate && *ctl.gate == 0) return;
     }
-    step_body<L, T, BC, INIT, OUT, NTS>(p, b, ctl, xcd_tile(blockIdx.x, gridDim.x, p.xcd_remap), blockIdx.x);
+    step_body<L, T, BC, INIT, NTS>(p, b, ctl, xcd_tile(blockIdx.x, gridDim.x, p.xcd_remap), blockIdx.x);
 }
 
 // Batched step: one launch advances every lattice of a batch by one step.
@@ -1398,7 +1407,7 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
 // taken -- the work list of the active lattices, compacted on the device
 // before the steps -- so that the active lattices' tiles spread over all
 // XCDs whatever lattices are left out; the other workgroups return at once.
-template <class L, class T, int BC, bool OUT, bool NTS>
+template <class L, class T, int BC, bool NTS>
 __global__ void __launch_bounds__(256) k_step_batch(const BatchLattice* lat, const uint2* work,
                                                     const long long* clock, int k, int write_last,
                                                     const int* count) {
@@ -1414,7 +1423,7 @@ __global__ void __launch_bounds__(256) k_step_batch(const BatchLattice* lat, con
     c.write_diag = write_last;
     c.gate = nullptr;
     const KBuffers bb = d.buf[(c.t - 1) & 1];
-    step_body<L, T, BC, false, OUT, NTS>(p, bb, c, w.y, w.y);
+    step_body<L, T, BC, false, NTS>(p, bb, c, w.y, w.y);
 }
 
 __global__ void k_clock_add(long long* clock, long long add) {
@@ -1537,27 +1546,22 @@ static unsigned window_bytes(dim3 bl) {
     return (bl.x + 2) * (bl.y + 2) * (L::D == 3 ? 3u : 1u) * (unsigned)sizeof(Rec8<float>);
 }
 
-template <class L, class T, int BC, bool INIT, bool OUT, bool NTS = false>
+template <class L, class T, int BC, bool INIT, bool NTS = false>
 static hipError_t go(const KParams& p, const KBuffers& b, const KCtl& c, dim3 g, dim3 bl, hipStream_t s) {
     const unsigned lds = window_bytes<L, T, INIT>(bl);
-    hipLaunchKernelGGL((k_step<L, T, BC, INIT, OUT, NTS>), g, bl, lds, s, p, b, c);
+    hipLaunchKernelGGL((k_step<L, T, BC, INIT, NTS>), g, bl, lds, s, p, b, c);
     return hipGetLastError();
 }
 
-// the initial step always writes the read-out (the standard column's uses the
-// generic channel instantiation); a later step takes the instantiation
-// without read-out unless its control asks for diagnostics or fields
+// the initial step (the standard column's uses the generic channel
+// instantiation); every later step of a lattice runs one instantiation
 template <class L, class T, int BC>
 static hipError_t go3(bool init, const KParams& p, const KBuffers& b, const KCtl& c, dim3 g, dim3 bl,
                       hipStream_t s) {
-    if (init) return go<L, T, BC == kBcColumn ? kBcGeneric : BC, true, true>(p, b, c, g, bl, s);
+    if (init) return go<L, T, BC == kBcColumn ? kBcGeneric : BC, true>(p, b, c, g, bl, s);
     // a lattice whose populations exceed the last-level cache stores them
     // with the nontemporal hint
-    if (c.write_diag || c.write_macro)
-        return p.nt_store ? go<L, T, BC, false, true, true>(p, b, c, g, bl, s)
-                          : go<L, T, BC, false, true, false>(p, b, c, g, bl, s);
-    return p.nt_store ? go<L, T, BC, false, false, true>(p, b, c, g, bl, s)
-                      : go<L, T, BC, false, false, false>(p, b, c, g, bl, s);
+    return p.nt_store ? go<L, T, BC, false, true>(p, b, c, g, bl, s) : go<L, T, BC, false, false>(p, b, c, g, bl, s);
 }
 
 template <class L, class T>
@@ -1592,7 +1596,7 @@ hipError_t launch_step(int lattice, int storage, int bc, bool init, const KParam
     return hipErrorInvalidValue;
 }
 
-template <class L, class T, bool OUT, bool NTS>
+template <class L, class T, bool NTS>
 static hipError_t gob_out(int bc, const BatchLattice* lat, const uint2* work, long long nwork,
                           const long long* clock, int k, int write_last, const int* count, dim3 block,
                           hipStream_t s) {
@@ -1600,13 +1604,13 @@ static hipError_t gob_out(int bc, const BatchLattice* lat, const uint2* work, lo
     const unsigned lds = window_bytes<L, T, false>(block);
     switch (bc) {
         case kBcPeriodic:
-            hipLaunchKernelGGL((k_step_batch<L, T, kBcPeriodic, OUT, NTS>), g, block, lds, s, lat, work, clock, k, write_last, count);
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcPeriodic, NTS>), g, block, lds, s, lat, work, clock, k, write_last, count);
             break;
         case kBcGeneric:
-            hipLaunchKernelGGL((k_step_batch<L, T, kBcGeneric, OUT, NTS>), g, block, lds, s, lat, work, clock, k, write_last, count);
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcGeneric, NTS>), g, block, lds, s, lat, work, clock, k, write_last, count);
             break;
         case kBcColumn:
-            hipLaunchKernelGGL((k_step_batch<L, T, kBcColumn, OUT, NTS>), g, block, lds, s, lat, work, clock, k, write_last, count);
+            hipLaunchKernelGGL((k_step_batch<L, T, kBcColumn, NTS>), g, block, lds, s, lat, work, clock, k, write_last, count);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -1616,11 +1620,8 @@ static hipError_t gob_out(int bc, const BatchLattice* lat, const uint2* work, lo
 template <class L, class T>
 static hipError_t gob(int bc, bool nts, const BatchLattice* lat, const uint2* work, long long nwork,
                       const long long* clock, int k, int write_last, const int* count, dim3 block, hipStream_t s) {
-    if (nts)
-        return write_last ? gob_out<L, T, true, true>(bc, lat, work, nwork, clock, k, write_last, count, block, s)
-                          : gob_out<L, T, false, true>(bc, lat, work, nwork, clock, k, write_last, count, block, s);
-    return write_last ? gob_out<L, T, true, false>(bc, lat, work, nwork, clock, k, write_last, count, block, s)
-                      : gob_out<L, T, false, false>(bc, lat, work, nwork, clock, k, write_last, count, block, s);
+    if (nts) return gob_out<L, T, true>(bc, lat, work, nwork, clock, k, write_last, count, block, s);
+    return gob_out<L, T, false>(bc, lat, work, nwork, clock, k, write_last, count, block, s);
 }
 
 template <class L>

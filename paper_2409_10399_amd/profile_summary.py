@@ -38,9 +38,11 @@ def read_stats(path):
 
 
 def counter_per_dispatch(path, kernel_substr, counter):
-    """Mean of `counter` over the dispatches whose name contains
+    """Median of `counter` over the dispatches whose name contains
     kernel_substr; rows of one dispatch (one per XCD or SE instance) are
-    summed first.  Returns (mean, dispatches, kernel name)."""
+    summed first.  The median is the plain step: the last step of each
+    advance, the same kernel, also writes the FP64 read-out fields.
+    Returns (median, dispatches, kernel name)."""
     per = {}
     name = None
     with open(path, newline="") as fh:
@@ -51,8 +53,10 @@ def counter_per_dispatch(path, kernel_substr, counter):
             per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
     if not per:
         raise SystemExit(f"no {counter} rows for {kernel_substr!r} in {path}")
-    vals = list(per.values())
-    return sum(vals) / len(vals), len(vals), name
+    vals = sorted(per.values())
+    m = len(vals) // 2
+    med = vals[m] if len(vals) % 2 else 0.5 * (vals[m - 1] + vals[m])
+    return med, len(vals), name
 
 
 def cmd_stats(a):

@@ -82,6 +82,13 @@ def test_storage_sizes_of_every_mode():
     # population copies differ by 2 x 4 x 9 values x the byte difference per value
     assert sizes["fp32"] - sizes["mixed"] == 2 * 4 * 9 * n * (4 - 3)
     assert sizes["mixed"] - sizes["fp16"] == 2 * 4 * 9 * n * (3 - 2)
+    # FP64 records instead of FP32 ones: a D2Q9 record holds 2 + 2D = 6
+    # values (+ alpha_l) in each of two copies, the lag region S''_g, S''_l
+    # and Lambda', and the side buffers 2 copies x 2 faces x 2 x (2D + 2)
+    # values per face node add 4 bytes per value
+    assert cfg["n_gamma"] > 1
+    side = 2 * 2 * 2 * (2 * 2 + 2) * 128
+    assert sizes["fp32x"] - sizes["fp32"] == 4 * (n * (2 * (6 + 1) + 3) + side)
 
 
 def test_new_entry_points_validate_without_a_gpu():
