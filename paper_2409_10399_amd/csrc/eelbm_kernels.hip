@@ -1390,8 +1390,18 @@ __device__ __forceinline__ long long xcd_tile(long long id, long long nb, int re
 }
 
 
+// Waves per SIMD the compiler must leave room for.  The periodic D3Q19 FP16
+// step needs 174 VGPRs (2 waves); held to 168 (3 waves) it spills 9 values
+// to scratch and runs 5-8 % faster (128^3 / 256^3 columns).  The other D3Q19
+// steps spill 32 (BF16), 71 (FP32) or more values at 168 and ran slower, the
+// FP16 channel steps spill 41-61, and the D2Q9 steps fit 4 waves without
+// the hint.
+template <class L, class T, int BC>
+constexpr int kMinWaves = (L::D == 3 && BC == kBcPeriodic && std::is_same<T, __half>::value) ? 3 : 1;
+
 template <class L, class T, int BC, bool INIT, bool NTS>
-__global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b, const KCtl ctl) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<L, T, BC>)))
+k_step(const KParams p, const KBuffers b, const KCtl ctl) {
     if constexpr (INIT) {
         // a gated rebuild: the whole grid skips it when the device flag is 0
         if (ctl.gate && *ctl.gate == 0) return;
@@ -1408,9 +1418,9 @@ __global__ void __launch_bounds__(256) k_step(const KParams p, const KBuffers b,
 // before the steps -- so that the active lattices' tiles spread over all
 // XCDs whatever lattices are left out; the other workgroups return at once.
 template <class L, class T, int BC, bool NTS>
-__global__ void __launch_bounds__(256) k_step_batch(const BatchLattice* lat, const uint2* work,
-                                                    const long long* clock, int k, int write_last,
-                                                    const int* count) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<L, T, BC>)))
+k_step_batch(const BatchLattice* lat, const uint2* work, const long long* clock, int k, int write_last,
+             const int* count) {
     const long long nb = count ? (long long)*count : (long long)gridDim.x;
     if ((long long)blockIdx.x >= nb) return;
     const uint2 w = work[xcd_tile(blockIdx.x, nb, 1)];

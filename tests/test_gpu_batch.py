@@ -154,7 +154,7 @@ def test_batch_follows_members_rebuilt_at_another_time():
         assert b.diag()["nonfinite"] == 0
 
 
-@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 def test_batch_equals_members_alone_d3q19(storage):
     from paper_2409_10399_amd import Batch
     ws = members_3d()
