@@ -96,25 +96,38 @@ def cpu_baseline(steps=20, procs=None):
         span = max(d["t1"] for d in out) - min(d["t0"] for d in out)
         return sum(d["nodes"] for d in out) * steps / span / 1e6, span
 
-    # the FP64 periodic-box case (D2Q9 64x64, R = 10) on one core, for scale
-    box = code.replace("workloads.channel_2d()", "workloads.periodic_box_2d()").replace(
-        "o.step(%d)" % steps, "o.step(200)").replace("* steps", "* 200")
+    def one_core(body):
+        """MLUPS of one process running `body` (sets `lats` = [(cfg, fields, steps)])"""
+        src = ("import sys, time, json; sys.path.insert(0, %r)\n"
+               "import workloads\nfrom oracle import Oracle\n" % ROOT + body +
+               "os_ = [(Oracle(c, f), k) for c, f, k in lats]\n"
+               "t0 = time.time()\nfor o, k in os_: o.step(k)\nt1 = time.time()\n"
+               "n = sum(c['nx'] * c['ny'] * c.get('nz', 1) * k for c, f, k in lats)\n"
+               "print(json.dumps({'t': t1 - t0, 'updates': n}))\n")
+        pr = subprocess.run([sys.executable, "-c", src], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                            env=env, timeout=600)
+        if pr.returncode != 0:
+            raise RuntimeError(pr.stderr[-400:])
+        d = json.loads(pr.stdout.strip().splitlines()[-1])
+        return d["updates"] / d["t"] / 1e6
+
     try:
         one, dt1 = run(1)
         allc, dtn = run(procs)
-        pb = subprocess.run([sys.executable, "-c", box], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
-                            env=env, timeout=600)
-        if pb.returncode != 0:
-            raise RuntimeError(pb.stderr[-400:])
-        b = json.loads(pb.stdout.strip().splitlines()[-1])
-        box_mlups = b["nodes"] * 200 / (b["t1"] - b["t0"]) / 1e6
+        # for scale, on one core: the FP64 periodic box (D2Q9 64x64, R = 10,
+        # 200 steps), the D3Q19 64^3 periodic column with the 256^3 column's
+        # blob density (2 steps), and 8 members of the channel sweep (3 steps each)
+        box_mlups = one_core("lats = [workloads.periodic_box_2d() + (200,)]\n")
+        col_mlups = one_core("lats = [workloads.column_3d(n=64, nblobs=4) + (2,)]\n")
+        swp_mlups = one_core("lats = [(c, f, 3) for c, f in workloads.channel_sweep(8, seed=0)]\n")
     except (RuntimeError, subprocess.TimeoutExpired) as e:
         return {"error": str(e)[-400:]}
     return {"value": allc, "unit": "MLUPS", "cores": procs, "kind": "oracle",
             "sample": f"D2Q9 1024x1024 channel, {steps} steps per copy, NumPy FP64, {procs} single-thread "
                       f"copies at once ({dtn:.1f} s span); one copy alone: {one:.3f} MLUPS ({dt1:.1f} s)",
             "single_core": one, "host_cpus": ncpu, "cpu_model": model,
-            "periodic_box_64_single_core": box_mlups}
+            "periodic_box_64_single_core": box_mlups, "column_64_d3q19_single_core": col_mlups,
+            "sweep_8_members_single_core": swp_mlups}
 
 
 def surrogate_leg():
