@@ -171,6 +171,25 @@ def test_batch_equals_members_alone_d3q19(storage):
                 assert np.array_equal(a.read(k), b.read(k)), (storage, n, k)
 
 
+def test_batch_equals_members_alone_d3q19_periodic_fp16():
+    """Periodic D3Q19 columns in FP16 (the step instantiation compiled for
+    three waves per SIMD, alone and batched): identical bits."""
+    from paper_2409_10399_amd import Batch
+    ws = [workloads.column_3d(n=n, nblobs=2, seed=50 + n, background=0.01) for n in (16, 24)]
+    alone = _lattices(ws, "fp16")
+    batched = _lattices(ws, "fp16")
+    batch = Batch(batched, tile=(64, 2), graph_steps=4)
+    for n in (4, 7):
+        batch.advance(n)
+        for lat in alone:
+            lat.set_launch(64, 2)
+            lat.advance(n)
+        for a, b in zip(alone, batched):
+            for k in FIELDS:
+                assert np.array_equal(a.read(k), b.read(k)), (n, k)
+            assert b.diag()["nonfinite"] == 0
+
+
 def test_batch_member_matches_oracle():
     from paper_2409_10399_amd import Batch
     ws = members()[:3]
@@ -251,13 +270,22 @@ def test_batch_active_flags_and_gated_rebuilds():
     batch.set_active(flags)
     before = [{k: b.read(k) for k in FIELDS} for b in batched]
     batch.advance(8)
+    def state(lat):
+        # what a failure needs to be read: time, tile, diagnostics, field ranges
+        d = lat.diag()
+        rng = {k: (float(np.min(v)), float(np.max(v))) for k, v in ((k, lat.read(k)) for k in FIELDS)}
+        return dict(t=lat.t, tile=lat.get_launch(), nonfinite=d["nonfinite"], alpha_g=d["alpha_g"],
+                    a_g=d["a_g"], ranges=rng)
+
     for i, (a, b) in enumerate(zip(alone, batched)):
         for k in FIELDS:
             if flags[i]:
                 if k == FIELDS[0]:
                     a.set_launch(64, 4)
                     a.advance(8)
-                assert np.array_equal(a.read(k), b.read(k)), (i, k)
+                ra, rb = a.read(k), b.read(k)
+                if not np.array_equal(ra, rb):
+                    raise AssertionError((i, k, "alone", state(a), "batched", state(b)))
             else:
                 assert np.array_equal(before[i][k], b.read(k)), (i, k)  # left as it was
     # rebuild every member at t = 8 from other fields (the same channels
