@@ -971,6 +971,11 @@ int eelbm_batch_create(eelbm_handle* const* members, int32_t n, int32_t tile_x, 
     hipError_t e = hipStreamCreate(&b->own);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+    // the caller's memory may still be in use by work queued on the caller's
+    // stream (an allocator that reuses a block as soon as that stream moves
+    // on): the uploads below wait for it
+    if (e == hipSuccess) e = hipEventRecord(b->ev_in, b->user);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->own, b->ev_in, 0);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->mem + b->off_lat, lat.data(), lat.size() * sizeof(BatchLattice), hipMemcpyHostToDevice,
                            b->own);
