@@ -89,6 +89,10 @@ def test_storage_sizes_of_every_mode():
     assert cfg["n_gamma"] > 1
     side = 2 * 2 * 2 * (2 * 2 + 2) * 128
     assert sizes["fp32x"] - sizes["fp32"] == 4 * (n * (2 * (6 + 1) + 3) + side)
+    # D3Q19: records of 2 + 2D = 8 values; a periodic column has no side buffers
+    cfg3, _ = workloads.column_3d(n=32, nblobs=1)
+    s3 = {s: b.state_bytes(cfg3, s) for s in ("fp32", "fp32x")}
+    assert s3["fp32x"] - s3["fp32"] == 4 * 32 ** 3 * (2 * (8 + 1) + 3)
 
 
 def test_new_entry_points_validate_without_a_gpu():
